@@ -1,0 +1,220 @@
+"""Pins of the oracle's nested method (Sec. 4, App. C) and of the
+preconditioning formulas (Eqs. precond, proofprec, popt, condimp, condimpNH)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import nks_inputs as I
+from oracle import closedform, dirac, krylov, nested, precond, signfun
+
+M0 = 1.6
+
+
+# ---------------------------------------------------------------- printed numbers
+def test_printed_p_opt_and_gain_hermitian():
+    # Fig. 4 caption: z_min = Delta = 0.055, z_max = 5.26 -> p_opt ~ 1.86, F = 19.3
+    assert precond.p_opt(0.055, 5.26) == pytest.approx(1.86, abs=0.005)
+    assert precond.gain_hermitian(0.055, 5.26) == pytest.approx(19.3, abs=0.1)
+    # "almost improved by a factor 20" and F ~ 2 sqrt(z_max/z_min)
+    assert precond.gain_hermitian_approx(0.055, 5.26) == pytest.approx(19.56, abs=0.01)
+
+
+def test_printed_p_opt_nonhermitian():
+    # Fig. 6 caption: z_min = 0.107, z_max = 5.243 -> p_opt ~ 1.335
+    assert precond.p_opt(0.107, 5.243) == pytest.approx(1.335, abs=0.0005)
+
+
+def test_printed_circle_gain():
+    # Fig. 5 / Eq. condimpNH: circle C(2.55, 2.45) -> F = 3.84
+    m, r = 2.55, 2.45
+    assert precond.gain_circle(m, r) == pytest.approx(3.84, abs=0.005)
+    assert precond.gain_circle_gap(m, m - r) == pytest.approx(precond.gain_circle(m, r))
+    d, dp = precond.circle_distances(m, r)
+    assert dp / d == pytest.approx(precond.gain_circle(m, r), rel=1e-12)
+    assert dp == pytest.approx((m * m - r * r) / m ** 2, rel=1e-12)
+    assert precond.gain_circle_gap(10.0, 1e-6) == pytest.approx(4.0, abs=1e-5)
+
+
+def test_circle_maps_to_circle():
+    # with p_opt the image of C(m, r) is C(m', r')
+    m, r = 2.55, 2.45
+    p = precond.circle_p_opt(m, r)
+    th = np.linspace(0, 2 * np.pi, 721)
+    z = m + r * np.exp(1j * th)
+    zp = precond.precond_map(z, p)
+    mp, rp = precond.circle_image(m, r)
+    assert np.allclose(np.abs(zp - mp), rp, atol=1e-12)
+
+
+def test_hermitian_p_opt_balances_extremes():
+    zmin, zmax = 0.07, 2.9
+    p = precond.p_opt(zmin, zmax)
+    a = precond.precond_map(zmin, p).real
+    b = precond.precond_map(zmax, p).real
+    assert a == pytest.approx(b)
+    assert a == pytest.approx(precond.zprime_max(zmin, zmax))
+    # the transformed smallest value is 1
+    assert precond.precond_map(1 / p, p).real == pytest.approx(1.0)
+
+
+def test_precond_preserves_sign_scalar():
+    rng = np.random.default_rng(0)
+    z = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    for p in (0.3, 1.0, 1.86, 7.0):
+        assert np.all(np.sign(precond.precond_map(z, p).real) == np.sign(z.real))
+
+
+@pytest.mark.parametrize("herm", [True, False])
+def test_precond_preserves_matrix_sign(herm):
+    # Eq. proofprec: sgn(H') = sgn(H) for any p > 0, on random tridiagonals
+    rng = np.random.default_rng(3 + herm)
+    k = 30
+    a = rng.standard_normal(k) * 2
+    b = rng.uniform(0.2, 1.0, k - 1)
+    if herm:
+        H = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    else:
+        H = (np.diag(a + 0.2j * rng.standard_normal(k)) + np.diag(b, -1)
+             + np.diag(b * np.exp(0.3j * rng.standard_normal(k - 1)), 1))
+    s = signfun.sign_eig(H, hermitian=herm)
+    for p in (0.5, 1.0, 2.3):
+        Hp = 0.5 * (p * H + np.linalg.inv(p * H))
+        assert np.linalg.norm(signfun.sign_eig(Hp, hermitian=herm) - s) < 1e-9 * np.linalg.norm(s)
+
+
+# ---------------------------------------------------------------- LAPACK steps
+@pytest.mark.parametrize("cplx", [False, True])
+def test_tridiag_lu_solve_matches_dense(cplx):
+    rng = np.random.default_rng(5)
+    k = 57
+    dt = complex if cplx else float
+    sub = rng.standard_normal(k - 1).astype(dt)
+    dia = rng.standard_normal(k).astype(dt) * 0.1   # forces row interchanges
+    sup = rng.standard_normal(k - 1).astype(dt)
+    if cplx:
+        sub = sub + 1j * rng.standard_normal(k - 1)
+        sup = sup + 1j * rng.standard_normal(k - 1)
+    T = np.diag(dia) + np.diag(sub, -1) + np.diag(sup, 1)
+    lu = nested.TridiagLU(sub, dia, sup)
+    assert lu.info == 0
+    assert np.any(lu.ipiv != np.arange(1, k + 1))
+    v = rng.standard_normal(k).astype(dt)
+    assert np.allclose(lu.solve(v), np.linalg.solve(T, v), atol=1e-10)
+    assert np.allclose(lu.solve(v, "C"), np.linalg.solve(T.conj().T, v), atol=1e-10)
+    assert np.allclose(nested.tridiag_matvec(sub, dia, sup, v), T @ v, atol=1e-13)
+
+
+# ---------------------------------------------------------------- nested method
+_OPS = {}
+
+
+def _op(mu, dims=(3, 3, 3, 3), eps=0.2, seed=31):
+    key = (mu, dims, eps, seed)
+    if key not in _OPS:
+        _OPS[key] = dirac.Operator(I.su3_links(dims, eps, seed), dims, M0, mu)
+    return _OPS[key]
+
+
+_DENSE_SIGN = {}
+
+
+def _exact(op, b):
+    key = (op.mu, op.dims)
+    if key not in _DENSE_SIGN:
+        from oracle.signfun import sign_eig
+        _DENSE_SIGN[key] = sign_eig(op.dense(), hermitian=op.hermitian)
+    return (_DENSE_SIGN[key] @ np.ravel(b)).reshape(np.shape(b))
+
+
+def test_unpreconditioned_inner_space_is_leading_block_bit_exact():
+    # Sec. 4.1: K_ell(H_k, e_1) only sees the ell x ell upper-left block of H_k
+    op = _op(0.0)
+    b = I.gaussian_source(op.dims, 1).ravel()
+    kr = krylov.lanczos(op.matvec, b, 80)
+    ell = 20
+    c, info = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, True, ell,
+                                         precondition=False)
+    Tl = kr.H()[:ell, :ell].real
+    s, _, _ = signfun.rhi(Tl)
+    assert np.array_equal(c[:ell], s[:, 0])
+    assert np.all(c[ell:] == 0)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_nested_with_ell_equal_k_matches_non_nested(mu):
+    op = _op(mu)
+    b = I.gaussian_source(op.dims, 2)
+    k = 60
+    y1, info = nested.sign_apply(op, b, k, k, force_nested=True)
+    y2, _ = nested.nonnested_sign_apply(op, b, k)
+    assert info["nested"] and info["ell"] >= k - 2  # may stop at an invariant subspace
+    assert nested.rel_err(y1, y2) < 1e-9
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_nested_converges_to_exact_sign(mu):
+    op = _op(mu)
+    b = I.gaussian_source(op.dims, 3)
+    ref = _exact(op, b)
+    errs = []
+    for k in (100, 200, 300):
+        y, info = nested.sign_apply(op, b, k, 60)
+        errs.append(nested.rel_err(y, ref))
+    assert errs[0] > errs[1] > errs[2] or errs[2] < 1e-11
+    assert errs[2] < 1e-8
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_ell_opt_much_smaller_than_k(mu):
+    # Sec. 4.2: the nested error reaches the non-nested one for ell << k
+    op = _op(mu)
+    b = I.gaussian_source(op.dims, 4)
+    k = 200
+    ref = _exact(op, b)
+    y_nn, _ = nested.nonnested_sign_apply(op, b, k)
+    e_nn = nested.rel_err(y_nn, ref)
+    y, _ = nested.sign_apply(op, b, k, 50)
+    assert nested.rel_err(y, ref) < 1.5 * e_nn + 1e-12
+    # the unpreconditioned inner space at the same ell is far worse
+    y_np, _ = nested.sign_apply(op, b, k, 50, precondition=False)
+    assert nested.rel_err(y_np, ref) > 10 * e_nn
+
+
+def test_result_insensitive_to_p_once_converged():
+    op = _op(0.0)
+    b = I.gaussian_source(op.dims, 5)
+    y1, i1 = nested.sign_apply(op, b, 200, 80)
+    y2, i2 = nested.sign_apply(op, b, 200, 80, p=0.8 * i1["p"])
+    assert nested.rel_err(y1, y2) < 1e-9
+
+
+def test_error_estimate_tracks_true_error():
+    # Sec. 3: eps = |sgn(sgn(x)) - x| / 2|x| is consistent with the true error
+    op = _op(0.0)
+    x = I.ones_source(op.dims)
+    ref = _exact(op, x)
+    for k in (40, 80):
+        y, _ = nested.sign_apply(op, x, k, k)
+        true = nested.rel_err(y, ref)
+        est = nested.error_estimate(op, x, k, k)
+        assert 0.1 * true < est < 10 * true
+
+
+def test_ritz_extremes_hermitian_and_general_agree():
+    op = _op(0.0)
+    kr = krylov.lanczos(op.matvec, I.gaussian_source(op.dims, 6).ravel(), 40)
+    a = nested.ritz_extremes(kr.alpha, kr.beta, kr.beta, True)
+    b = nested.ritz_extremes(kr.alpha.astype(complex), kr.beta.astype(complex),
+                             kr.beta.astype(complex), False)
+    assert np.allclose(a, b, rtol=1e-10)
+
+
+def test_pure_gauge_nested_full_method():
+    dims = (4, 4, 4, 4)
+    g = I.random_su3_field(dims, 44)
+    for mu in (0.0, 0.3):
+        op = dirac.Operator(I.pure_gauge_links(g), dims, M0, mu)
+        b = I.gaussian_source(dims, 45)
+        ref = closedform.pure_gauge_sign_apply(b, g, dims, M0, mu)
+        y, info = nested.sign_apply(op, b, 200, 80)
+        assert nested.rel_err(y, ref) < 1e-10
