@@ -1,0 +1,203 @@
+/*
+ * nks.h -- C ABI of libnks, the nested Krylov-Ritz matrix sign function
+ * (Bloch & Heybrock, "A nested Krylov subspace method to compute the sign
+ * function of large complex matrices") for the lattice operator
+ *
+ *     A = gamma5 D_w(mu),   D_w(mu) as defined in Sec. 2 of the paper,
+ *
+ * on AMD MI355X (gfx950).  The library computes y ~ sgn(A) b by
+ *   (1) k steps of Lanczos (mu = 0, App. A) or two-sided Lanczos (mu != 0,
+ *       App. B) on A from b,
+ *   (2) the nested step of Sec. 4.1 / App. C: LU of p H_k, ell steps of
+ *       (two-sided) Lanczos on H_k' = (p H_k + (p H_k)^{-1}) / 2 from e_1,
+ *       Roberts-Higham iteration (Eq. Roberts) on H_ell,
+ *   (3) the lift y = |b| V_k V_ell sgn(H_ell) e_1 (Eq. nested).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - dims = {Lx, Ly, Lz, Lt}, each >= 2, periodic in all four directions.
+ *   Site index s = x + Lx*(y + Ly*(z + Lz*t)); V = Lx*Ly*Lz*Lt; n = 12 V.
+ * - Vectors (b, x, in, out) are DEVICE pointers to n interleaved complex128
+ *   values (re, im), component index 12*s + 3*spin + colour.
+ * - Links are a DEVICE pointer to 4*9*V complex128 values, index
+ *   ((s*4 + nu)*3 + row)*3 + col, nu = 0..3 for x, y, z, t.  Link U_{s,nu}
+ *   transports from site s to s + nu_hat: the hop of D_w(mu) that lands on
+ *   y brings psi(y - nu_hat) with (1 + gamma_nu) U_{y-nu_hat,nu} and
+ *   psi(y + nu_hat) with (1 - gamma_nu) U_{y,nu}^dagger (Sec. 2).
+ * - Dirac matrices: chiral basis, gamma_k = [[0, -i sigma_k], [i sigma_k, 0]]
+ *   (k = 1..3), gamma_4 = [[0, 1], [1, 0]], gamma5 = diag(1, 1, -1, -1).
+ * - m0 > 0 is the negative Wilson mass: m_w = -m0 in (-2, 0) and
+ *   kappa = 1 / (8 + 2 m_w).  mu is the real chemical potential; the forward
+ *   time hop carries e^{+mu}, the backward one e^{-mu}.
+ * - stream arguments are hipStream_t passed as void* (NULL = default
+ *   stream).  Calls are asynchronous on the stream unless stated otherwise;
+ *   the caller keeps every buffer alive until the stream has completed.
+ * - Ownership: the caller owns b, x, links and workspaces; the library
+ *   owns only what it allocates inside nks_ctx / nks_lattice and never
+ *   frees caller memory or keeps caller pointers past the call.
+ * - Errors: every int-returning function returns NKS_OK or an NKS_E_* code;
+ *   nks_last_error(ctx) gives a message for the last failure on ctx.
+ *   Outcomes found on the device (breakdown, no convergence) come back in
+ *   nks_stats.status.
+ * - A context is not thread-safe: use one nks_ctx per host thread.
+ */
+#ifndef NKS_H
+#define NKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NKS_ABI_VERSION 1
+
+enum nks_status {
+    NKS_OK = 0,
+    NKS_E_INVALID = 1,      /* bad argument (sizes, pointers, m0 out of range) */
+    NKS_E_NOMEM = 2,        /* workspace too small or allocation failure */
+    NKS_E_HIP = 3,          /* HIP runtime or launch error */
+    NKS_E_UNSUPPORTED = 4,  /* valid but not supported (e.g. non-nested k too large) */
+    NKS_E_BREAKDOWN = 5,    /* serious two-sided Lanczos breakdown (App. B) */
+    NKS_E_NOCONV = 6        /* Roberts-Higham or ell-doubling did not converge */
+};
+
+enum nks_precision {
+    NKS_FP64 = 0,   /* every vector and scalar in float64 */
+    NKS_MIXED = 1   /* float32 stencil and basis vectors, float64 recurrence
+                       coefficients, nested step and lift accumulation */
+};
+
+enum nks_policy {
+    NKS_POLICY_FIXED = 0,     /* use opts.k / opts.ell as given */
+    NKS_POLICY_DOUBLING = 1,  /* ell: double from 16 until the coefficient change
+                                 is <= tol/10; k: checkpoints every 100 steps until
+                                 the change is <= tol/4 (k stays <= opts.k) */
+    NKS_POLICY_LEARNED = 2    /* predicted by the loaded MLP, verified by one
+                                 doubling step, falls back to DOUBLING */
+};
+
+/* Options of one sign application.  Initialise with nks_opts_default(). */
+typedef struct nks_opts {
+    size_t size;          /* sizeof(nks_opts), for versioning */
+    int k;                /* outer Krylov size (max k under a policy); rounded up to even */
+    int ell;              /* inner Krylov size; rounded up to even; ell >= k -> non-nested RHi on H_k */
+    double tol;           /* target relative accuracy for the policies */
+    int precision;        /* enum nks_precision */
+    double p;             /* preconditioner factor of Eq. precond; <= 0 -> p_opt of Eq. popt
+                             estimated from the Ritz values of H_k */
+    int k_policy;         /* enum nks_policy */
+    int ell_policy;       /* enum nks_policy */
+    int max_rhi_iter;     /* Roberts-Higham iteration cap (default 50) */
+    double rhi_tol;       /* relative Frobenius change that ends RHi (default 1e-14) */
+    unsigned flags;       /* reserved, 0 */
+} nks_opts;
+
+/* Per-result report (filled after the stream completes). */
+typedef struct nks_stats {
+    int status;           /* NKS_OK, NKS_E_BREAKDOWN or NKS_E_NOCONV */
+    int k_used;           /* outer basis size actually built (lucky breakdown -> smaller) */
+    int ell_used;         /* inner basis size actually used (0 = non-nested) */
+    int rhi_iters;        /* Roberts-Higham iterations */
+    double p_used;        /* preconditioner factor used */
+    double z_min, z_max;  /* Ritz-value extremes |theta| used for p (0 if p was given) */
+    double b_norm;        /* |b| */
+    int breakdown_iter;   /* iteration of a serious breakdown, else 0 */
+    double inner_delta;   /* last ell-doubling relative change (policies), else 0 */
+    double outer_delta;   /* last k-checkpoint relative change (policies), else 0 */
+    float ms_outer, ms_nested, ms_lift;  /* device time per phase (single-job calls) */
+} nks_stats;
+
+typedef struct nks_ctx nks_ctx;
+typedef struct nks_lattice nks_lattice;
+
+/* One job of a batched call: x ~ sgn(A) b on lattice lat. */
+typedef struct nks_job {
+    nks_lattice* lat;
+    const void* b;        /* device, n complex128 */
+    void* x;              /* device, n complex128 */
+    const nks_opts* opts;
+} nks_job;
+
+/* Fill *o with defaults: k=200, ell=50, tol=1e-8, FP64, p auto, FIXED policies. */
+void nks_opts_default(nks_opts* o);
+
+/* Create a context on HIP device `device` (makes it current). */
+int nks_create(int device, nks_ctx** out);
+void nks_destroy(nks_ctx* ctx);
+const char* nks_last_error(nks_ctx* ctx);
+const char* nks_status_str(int status);
+
+/* Copy the links (device complex128, layout above) into the lattice's own
+ * float64 and float32 structure-of-arrays copies.  Params default to
+ * m0 = 1.6, mu = 0.  Blocks until the copy is done. */
+int nks_lattice_create(nks_ctx* ctx, const int32_t dims[4], const void* links_dev,
+                       nks_lattice** out);
+/* Set m0 (m_w = -m0 must lie in (-2, 0)) and mu.  mu == 0 selects Lanczos,
+ * mu != 0 two-sided Lanczos. */
+int nks_lattice_set_params(nks_lattice* lat, double m0, double mu);
+void nks_lattice_destroy(nks_lattice* lat);
+
+/* out = A in (dagger = 0) or A^dagger in (dagger = 1), A = gamma5 D_w(mu);
+ * A(mu)^dagger = gamma5 D_w(-mu).  precision NKS_MIXED runs the float32
+ * stencil (inputs and outputs stay complex128).  in and out must not alias. */
+int nks_apply_op(nks_lattice* lat, const void* in, void* out, int dagger, int precision,
+                 void* stream);
+
+/* Device workspace bytes needed by nks_sign_apply_batch for these jobs (and
+ * by nks_sign_apply for one job).  Dominated by the outer basis: n*k*16
+ * bytes per FP64 job, n*k*8 per mixed job. */
+int nks_workspace_size(nks_ctx* ctx, int njobs, const nks_job* jobs, size_t* bytes);
+
+/* x ~ sgn(A) b (Eq. nested; non-nested when ell >= k).  ws is a device
+ * buffer of at least nks_workspace_size bytes.  If stats != NULL the call
+ * waits for the stream and fills *stats. */
+int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
+                   const nks_opts* opts, void* ws, size_t ws_bytes, void* stream,
+                   nks_stats* stats);
+
+/* Many jobs in one call: jobs on the same lattice share each stencil sweep
+ * over the links; the whole launch sequence is captured once into a HIP
+ * graph and replayed on later calls with the same job shapes.  stats is
+ * NULL or an array of njobs entries (then the call waits for the stream). */
+int nks_sign_apply_batch(nks_ctx* ctx, int njobs, const nks_job* jobs, void* ws,
+                         size_t ws_bytes, void* stream, nks_stats* stats);
+
+/* Row-level entry points (the steps of App. C one at a time). */
+
+/* Steps 1-2 of the method: build the outer basis from b and return the
+ * tridiagonal Ritz matrix on the host: alpha[k] (H(j,j)), beta[k-1]
+ * (H(j+1,j)), gamma[k-1] (H(j,j+1)), each as interleaved complex128
+ * (imaginary parts 0 when mu = 0).  Waits for the stream. */
+int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opts* opts,
+                    void* ws, size_t ws_bytes, void* stream, double* alpha_host,
+                    double* beta_host, double* gamma_host, nks_stats* stats);
+
+/* Steps 3-5 on a given tridiagonal H_k (host arrays as returned by
+ * nks_outer_basis; hermitian != 0 treats it as real symmetric): returns
+ * c ~ sgn(H_k) e_1 (k interleaved complex128 on the host).  Waits. */
+int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double* beta_host,
+                    const double* gamma_host, int hermitian, const nks_opts* opts,
+                    double* c_host, nks_stats* stats);
+
+/* Measurement support.  When enabled on a context, sign applications bracket
+ * every 8th launch of each kernel class with HIP events on the call's stream
+ * (sampling keeps the timing overhead negligible).  nks_profile_read waits
+ * for those events, returns the number of timed launches, their summed
+ * device time and their summed algorithmic bytes (what each launch must move
+ * at minimum: inputs read once, outputs written once), and resets the class. */
+enum nks_kernel_class {
+    NKS_K_STENCIL = 0,   /* stencil pass of an outer iteration (A v, two-sided also A^dagger w) */
+    NKS_K_RECUR = 1,     /* recurrence pass of an outer iteration */
+    NKS_K_NESTED = 2,    /* nested step (steps 3-5), one launch per batch */
+    NKS_K_LIFT = 3,      /* lift y = |b| V_k c, one launch per lattice group */
+    NKS_K_COUNT = 4
+};
+int nks_profile_enable(nks_ctx* ctx, int enable);
+int nks_profile_read(nks_ctx* ctx, int kernel_class, int* launches, double* total_ms, double* alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NKS_H */

@@ -1,0 +1,356 @@
+"""Python binding of libnks (nested Krylov-Ritz sgn(A) b on MI355X).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libnks.so``.  PyTorch supplies device memory and the current stream.
+
+    import torch, paper_0912_4457_amd as nks
+    ctx = nks.Context()
+    lat = nks.Lattice(ctx, dims, links)          # links: complex128 CUDA tensor
+    lat.set_params(m0=1.6, mu=0.0)
+    x, st = nks.sign_apply(lat, b, k=200, ell=50)
+
+Vector layout: complex128, ``12*site + 3*spin + colour`` with
+``site = x + Lx*(y + Ly*(z + Lz*t))``; links ``((site*4 + nu)*3 + row)*3 + col``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "FP64", "MIXED", "POLICY_FIXED", "POLICY_DOUBLING", "POLICY_LEARNED",
+    "NKSError", "lib", "Context", "Lattice", "apply_op", "sign_apply", "sign_apply_batch",
+    "outer_basis", "nested_step", "workspace_size", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnks.so")
+
+FP64, MIXED = 0, 1
+POLICY_FIXED, POLICY_DOUBLING, POLICY_LEARNED = 0, 1, 2
+_PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+
+STATUS = {0: "ok", 1: "invalid", 2: "nomem", 3: "hip", 4: "unsupported", 5: "breakdown", 6: "noconv"}
+
+
+class NKSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libnks error {code} ({STATUS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_size_t), ("k", ctypes.c_int), ("ell", ctypes.c_int), ("tol", ctypes.c_double),
+        ("precision", ctypes.c_int), ("p", ctypes.c_double), ("k_policy", ctypes.c_int),
+        ("ell_policy", ctypes.c_int), ("max_rhi_iter", ctypes.c_int), ("rhi_tol", ctypes.c_double),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("k_used", ctypes.c_int), ("ell_used", ctypes.c_int),
+        ("rhi_iters", ctypes.c_int), ("p_used", ctypes.c_double), ("z_min", ctypes.c_double),
+        ("z_max", ctypes.c_double), ("b_norm", ctypes.c_double), ("breakdown_iter", ctypes.c_int),
+        ("inner_delta", ctypes.c_double), ("outer_delta", ctypes.c_double),
+        ("ms_outer", ctypes.c_float), ("ms_nested", ctypes.c_float), ("ms_lift", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["status_str"] = STATUS.get(self.status, "?")
+        return d
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("lat", ctypes.c_void_p), ("b", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("opts", ctypes.POINTER(Opts))]
+
+
+# exported symbols and their C signatures (kept in sync with include/nks.h)
+_VP, _I, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_PD = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "nks_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "nks_create": (_I, [_I, ctypes.POINTER(_VP)]),
+    "nks_destroy": (None, [_VP]),
+    "nks_last_error": (ctypes.c_char_p, [_VP]),
+    "nks_status_str": (ctypes.c_char_p, [_I]),
+    "nks_lattice_create": (_I, [_VP, ctypes.POINTER(ctypes.c_int32), _VP, ctypes.POINTER(_VP)]),
+    "nks_lattice_set_params": (_I, [_VP, _D, _D]),
+    "nks_lattice_destroy": (None, [_VP]),
+    "nks_apply_op": (_I, [_VP, _VP, _VP, _I, _I, _VP]),
+    "nks_workspace_size": (_I, [_VP, _I, ctypes.POINTER(Job), ctypes.POINTER(_SZ)]),
+    "nks_sign_apply": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
+    "nks_sign_apply_batch": (_I, [_VP, _I, ctypes.POINTER(Job), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
+    "nks_outer_basis": (_I, [_VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, _PD, _PD, _PD,
+                             ctypes.POINTER(Stats)]),
+    "nks_nested_step": (_I, [_VP, _I, _PD, _PD, _PD, _I, ctypes.POINTER(Opts), _PD, ctypes.POINTER(Stats)]),
+    "nks_profile_enable": (_I, [_VP, _I]),
+    "nks_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_int), _PD, _PD]),
+}
+
+KERNEL_CLASSES = {"stencil": 0, "recurrence": 1, "nested": 2, "lift": 3}
+
+_LIB = None
+
+
+def lib():
+    """Load libnks.so (built in-tree); raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_0912_4457_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libnks needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50, rhi_tol=1e-14,
+              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED) -> Opts:
+    o = Opts()
+    lib().nks_opts_default(ctypes.byref(o))
+    o.k, o.ell, o.tol = int(k), int(ell), float(tol)
+    o.precision = _PREC[precision]
+    o.p = 0.0 if p is None else float(p)
+    o.max_rhi_iter, o.rhi_tol = int(max_rhi_iter), float(rhi_tol)
+    o.k_policy, o.ell_policy = int(k_policy), int(ell_policy)
+    return o
+
+
+class Context:
+    """One libnks context on the current HIP device."""
+
+    def __init__(self, device: int | None = None):
+        torch = _torch()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        rc = lib().nks_create(self.device, ctypes.byref(h))
+        if rc:
+            raise NKSError(rc, "nks_create failed")
+        self.h = h
+        self._ws = None
+
+    def check(self, rc):
+        if rc:
+            raise NKSError(rc, lib().nks_last_error(self.h).decode())
+
+    def workspace(self, nbytes: int):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def profile(self, enable: bool = True):
+        """Sample kernel durations with HIP events (see nks_profile_enable)."""
+        self.check(lib().nks_profile_enable(self.h, int(bool(enable))))
+
+    def profile_read(self, kernel: str):
+        """(timed launches, summed ms, summed algorithmic bytes) for a kernel class."""
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        self.check(lib().nks_profile_read(self.h, KERNEL_CLASSES[kernel], ctypes.byref(n), ctypes.byref(ms),
+                                          ctypes.byref(by)))
+        return n.value, ms.value, by.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._ws = None
+            lib().nks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Lattice:
+    """Gauge links of a dims = (Lx, Ly, Lz, Lt) lattice copied into libnks."""
+
+    def __init__(self, ctx: Context, dims, links, m0: float = 1.6, mu: float = 0.0):
+        torch = _torch()
+        self.ctx = ctx
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        if not isinstance(links, torch.Tensor):
+            links = torch.from_numpy(np.ascontiguousarray(links, dtype=np.complex128))
+        links = links.to(device=f"cuda:{ctx.device}", dtype=torch.complex128).contiguous()
+        if links.numel() != 36 * self.V:
+            raise ValueError(f"links must hold 36*V = {36 * self.V} complex numbers, got {links.numel()}")
+        d = (ctypes.c_int32 * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        ctx.check(lib().nks_lattice_create(ctx.h, d, ctypes.c_void_p(links.data_ptr()), ctypes.byref(h)))
+        self.h = h
+        self.set_params(m0, mu)
+
+    @property
+    def n(self):
+        return 12 * self.V
+
+    def set_params(self, m0: float, mu: float):
+        self.ctx.check(lib().nks_lattice_set_params(self.h, float(m0), float(mu)))
+        self.m0, self.mu = float(m0), float(mu)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().nks_lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _vec(lat: Lattice, v):
+    torch = _torch()
+    if not isinstance(v, torch.Tensor):
+        v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.complex128))
+    v = v.to(device=f"cuda:{lat.ctx.device}", dtype=torch.complex128).contiguous()
+    if v.numel() != lat.n:
+        raise ValueError(f"vector must hold 12*V = {lat.n} complex numbers, got {v.numel()}")
+    return v
+
+
+def apply_op(lat: Lattice, v, dagger: bool = False, precision="fp64"):
+    """A v (or A^dagger v) with A = gamma5 D_w(mu); returns a new complex128 tensor."""
+    torch = _torch()
+    v = _vec(lat, v)
+    out = torch.empty_like(v)
+    lat.ctx.check(lib().nks_apply_op(lat.h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     int(bool(dagger)), _PREC[precision], _stream()))
+    return out
+
+
+def workspace_size(jobs) -> int:
+    ctx = jobs[0][0].ctx
+    arr, _keep = _job_array(jobs)
+    sz = ctypes.c_size_t()
+    ctx.check(lib().nks_workspace_size(ctx.h, len(jobs), arr, ctypes.byref(sz)))
+    return sz.value
+
+
+def _job_array(jobs):
+    """jobs: list of (lattice, b_tensor, x_tensor, Opts)."""
+    arr = (Job * len(jobs))()
+    keep = []
+    for i, (lat, b, x, o) in enumerate(jobs):
+        arr[i].lat = lat.h.value
+        arr[i].b = b.data_ptr() if b is not None else None
+        arr[i].x = x.data_ptr() if x is not None else None
+        arr[i].opts = ctypes.pointer(o)
+        keep.append(o)
+    return arr, keep
+
+
+def sign_apply(lat: Lattice, b, k: int = 200, ell: int = 50, p: float | None = None, precision="fp64",
+               tol: float = 1e-8, stats: bool = True, out=None, **kw):
+    """x ~ sgn(A) b by the nested Krylov-Ritz method; returns (x, stats dict or None)."""
+    torch = _torch()
+    b = _vec(lat, b)
+    x = torch.empty_like(b) if out is None else out
+    o = make_opts(k=k, ell=ell, tol=tol, precision=precision, p=p, **kw)
+    jobs = [(lat, b, x, o)]
+    arr, keep = _job_array(jobs)
+    ctx = lat.ctx
+    sz = ctypes.c_size_t()
+    ctx.check(lib().nks_workspace_size(ctx.h, 1, arr, ctypes.byref(sz)))
+    ws = ctx.workspace(sz.value)
+    st = Stats()
+    ctx.check(lib().nks_sign_apply(ctx.h, lat.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
+                                   ctypes.byref(st) if stats else None))
+    return x, (st.as_dict() if stats else None)
+
+
+def sign_apply_batch(jobs, stats: bool = True):
+    """jobs: list of dicts {lat, b, k, ell, p, precision} (or with 'x').
+
+    All jobs run in one call; jobs on the same lattice share each stencil
+    sweep.  Returns (list of x tensors, list of stats dicts or None)."""
+    torch = _torch()
+    spec = []
+    xs = []
+    for j in jobs:
+        lat = j["lat"]
+        b = _vec(lat, j["b"])
+        x = j.get("x")
+        x = torch.empty_like(b) if x is None else x
+        o = make_opts(k=j.get("k", 200), ell=j.get("ell", 50), tol=j.get("tol", 1e-8),
+                      precision=j.get("precision", "fp64"), p=j.get("p"))
+        spec.append((lat, b, x, o))
+        xs.append(x)
+    ctx = spec[0][0].ctx
+    arr, keep = _job_array(spec)
+    sz = ctypes.c_size_t()
+    ctx.check(lib().nks_workspace_size(ctx.h, len(spec), arr, ctypes.byref(sz)))
+    ws = ctx.workspace(sz.value)
+    sts = (Stats * len(spec))()
+    ctx.check(lib().nks_sign_apply_batch(ctx.h, len(spec), arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream(), sts if stats else None))
+    return xs, ([s.as_dict() for s in sts] if stats else None)
+
+
+def outer_basis(lat: Lattice, b, k: int, precision="fp64"):
+    """Steps 1-2 only: returns (alpha, beta, gamma) as complex numpy arrays and stats."""
+    b = _vec(lat, b)
+    o = make_opts(k=k, ell=2, precision=precision)
+    jobs = [(lat, b, None, o)]
+    arr, keep = _job_array(jobs)
+    ctx = lat.ctx
+    sz = ctypes.c_size_t()
+    ctx.check(lib().nks_workspace_size(ctx.h, 1, arr, ctypes.byref(sz)))
+    ws = ctx.workspace(sz.value)
+    kk = o.k + (o.k & 1)
+    a = np.zeros(2 * kk)
+    bb = np.zeros(2 * max(kk - 1, 1))
+    g = np.zeros(2 * max(kk - 1, 1))
+    st = Stats()
+    P = lambda arr_: arr_.ctypes.data_as(_PD)  # noqa: E731
+    ctx.check(lib().nks_outer_basis(ctx.h, lat.h, ctypes.c_void_p(b.data_ptr()), ctypes.byref(o),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(), P(a), P(bb), P(g),
+                                    ctypes.byref(st)))
+    ku = st.k_used
+    a = a.view(np.complex128)[:ku]
+    bb = bb.view(np.complex128)[:max(ku - 1, 0)]
+    g = g.view(np.complex128)[:max(ku - 1, 0)]
+    return a, bb, g, st.as_dict()
+
+
+def nested_step(ctx: Context, alpha, beta, gamma, hermitian: bool, ell: int, p: float | None = None,
+                max_rhi_iter: int = 50, rhi_tol: float = 1e-14):
+    """Steps 3-5 on a given tridiagonal H_k: returns (c ~ sgn(H_k) e_1, stats)."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.complex128)
+    k = alpha.size
+    beta = np.ascontiguousarray(beta if k > 1 else np.zeros(1), dtype=np.complex128)
+    gamma = np.ascontiguousarray(gamma if k > 1 else np.zeros(1), dtype=np.complex128)
+    o = make_opts(k=k, ell=ell, p=p, max_rhi_iter=max_rhi_iter, rhi_tol=rhi_tol)
+    c = np.zeros(k, dtype=np.complex128)
+    st = Stats()
+    P = lambda arr_: arr_.view(np.float64).ctypes.data_as(_PD)  # noqa: E731
+    ctx.check(lib().nks_nested_step(ctx.h, k, P(alpha), P(beta), P(gamma), int(bool(hermitian)), ctypes.byref(o),
+                                    P(c), ctypes.byref(st)))
+    return c, st.as_dict()

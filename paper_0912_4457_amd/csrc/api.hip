@@ -1,0 +1,663 @@
+// C ABI of libnks: contexts, lattices, workspace planning and the launch
+// sequence of a (batched) sign application.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "nks_internal.h"
+
+using namespace nks;
+
+struct ProfRecord {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct nks_ctx {
+    int device = 0;
+    std::string last_error;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // host copy of the last job table, kept alive while its upload may be in flight
+    std::vector<JobDesc> descs;
+    // sampled kernel timing (nks_profile_enable)
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfRecord> pending;
+    long long prof_count[NKS_K_COUNT] = {0, 0, 0, 0};
+};
+
+struct nks_lattice {
+    nks_ctx* ctx = nullptr;
+    Geom g{};
+    double m0 = 1.6, mu = 0.0, kappa = 1.0 / 4.8;
+    double2* links64 = nullptr;   // SoA [nu][row][col][site]
+    float2* links32 = nullptr;
+    double2* tmp = nullptr;       // 2 * 12V complex128 scratch for nks_apply_op
+};
+
+namespace {
+
+int fail(nks_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((ctx), NKS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+constexpr int NONNESTED_MAX = 1024;   // dense k x k RHi limit of the non-nested mode
+
+__global__ void links_to_soa(const double2* __restrict__ in, double2* __restrict__ o64, float2* __restrict__ o32,
+                             int V) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;   // e = q * V + site, q = nu*9 + row*3 + col
+    if (e >= 36 * V) return;
+    const int q = e / V, s = e - q * V;
+    const double2 u = in[(size_t)s * 36 + q];
+    o64[e] = u;
+    o32[e] = make_float2((float)u.x, (float)u.y);
+}
+
+int even_up(int k) { return k + (k & 1); }
+
+struct JobPlan {
+    int idx;            // index in the caller's job array
+    nks_lattice* lat;
+    int k, ell, precision, two_sided;
+    double p;
+    int max_rhi;
+    double rhi_tol;
+    int nblocks, lcap;
+    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_nest, end;
+};
+
+struct Plan {
+    std::vector<JobPlan> jobs;     // ordered by group
+    std::vector<std::pair<int, int>> groups;   // [start, count) per (lattice, precision)
+    size_t table_bytes = 0;
+    size_t total = 0;
+};
+
+int validate_opts(nks_ctx* ctx, const nks_opts* o) {
+    if (!o) return fail(ctx, NKS_E_INVALID, "opts is NULL");
+    if (o->size != sizeof(nks_opts)) return fail(ctx, NKS_E_INVALID, "opts->size mismatch (ABI version)");
+    if (o->k < 1) return fail(ctx, NKS_E_INVALID, "k must be >= 1");
+    if (o->ell < 1) return fail(ctx, NKS_E_INVALID, "ell must be >= 1");
+    if (o->precision != NKS_FP64 && o->precision != NKS_MIXED)
+        return fail(ctx, NKS_E_INVALID, "unknown precision");
+    if (o->max_rhi_iter < 1) return fail(ctx, NKS_E_INVALID, "max_rhi_iter must be >= 1");
+    if (!(o->rhi_tol > 0.0)) return fail(ctx, NKS_E_INVALID, "rhi_tol must be > 0");
+    if (o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED)
+        return fail(ctx, NKS_E_UNSUPPORTED, "policy not available in this entry point");
+    return NKS_OK;
+}
+
+int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
+    if (njobs < 1 || !jobs) return fail(ctx, NKS_E_INVALID, "no jobs");
+    std::vector<JobPlan> tmp;
+    for (int i = 0; i < njobs; ++i) {
+        const nks_job& J = jobs[i];
+        if (!J.lat) return fail(ctx, NKS_E_INVALID, "job lattice is NULL");
+        int rc = validate_opts(ctx, J.opts);
+        if (rc) return rc;
+        JobPlan jp{};
+        jp.idx = i;
+        jp.lat = J.lat;
+        jp.k = even_up(J.opts->k);
+        jp.ell = even_up(J.opts->ell);
+        jp.precision = J.opts->precision;
+        jp.two_sided = J.lat->mu != 0.0;
+        jp.p = J.opts->p;
+        jp.max_rhi = J.opts->max_rhi_iter;
+        jp.rhi_tol = J.opts->rhi_tol;
+        jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
+        if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
+            return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
+        jp.nblocks = (J.lat->g.V + OUTER_NT - 1) / OUTER_NT;
+        tmp.push_back(jp);
+    }
+    // group by (lattice, precision), keeping first-appearance order
+    std::vector<int> order;
+    std::vector<bool> used(tmp.size(), false);
+    for (size_t i = 0; i < tmp.size(); ++i) {
+        if (used[i]) continue;
+        const int start = (int)P.jobs.size();
+        for (size_t j = i; j < tmp.size(); ++j)
+            if (!used[j] && tmp[j].lat == tmp[i].lat && tmp[j].precision == tmp[i].precision) {
+                used[j] = true;
+                P.jobs.push_back(tmp[j]);
+            }
+        P.groups.push_back({start, (int)P.jobs.size() - start});
+    }
+    size_t off = align_up(sizeof(JobDesc) * P.jobs.size());
+    P.table_bytes = off;
+    for (auto& jp : P.jobs) {
+        const size_t n = (size_t)12 * jp.lat->g.V;
+        const size_t es = jp.precision == NKS_FP64 ? sizeof(double2) : sizeof(float2);
+        jp.off_vstore = off; off = align_up(off + (size_t)jp.k * n * es);
+        jp.off_lring = off; off = align_up(off + (jp.two_sided ? 2 * n * es : 0));
+        jp.off_part = off; off = align_up(off + sizeof(double2) * PS_COUNT * jp.nblocks);
+        jp.off_sc = off; off = align_up(off + sizeof(double2) * SC_COUNT * (jp.k + 2));
+        jp.off_status = off; off = align_up(off + sizeof(int) * ST_COUNT);
+        jp.off_report = off; off = align_up(off + sizeof(double) * RP_COUNT);
+        jp.off_omega = off; off = align_up(off + sizeof(double2) * jp.k);
+        jp.off_nest = off; off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided));
+        jp.end = off;
+    }
+    P.total = off;
+    return NKS_OK;
+}
+
+JobDesc make_desc(const JobPlan& jp, char* ws, const void* b, void* x) {
+    JobDesc d{};
+    d.b = static_cast<const double2*>(b);
+    d.x = static_cast<double2*>(x);
+    d.vstore = ws + jp.off_vstore;
+    d.lring = jp.two_sided ? ws + jp.off_lring : nullptr;
+    d.part = reinterpret_cast<double2*>(ws + jp.off_part);
+    d.sc = reinterpret_cast<double2*>(ws + jp.off_sc);
+    d.status = reinterpret_cast<int*>(ws + jp.off_status);
+    d.report = reinterpret_cast<double*>(ws + jp.off_report);
+    d.omega = reinterpret_cast<double2*>(ws + jp.off_omega);
+    d.nest = reinterpret_cast<double2*>(ws + jp.off_nest);
+    d.k = jp.k;
+    d.ell = jp.ell;
+    d.p = jp.p;
+    d.max_rhi = jp.max_rhi;
+    d.rhi_tol = jp.rhi_tol;
+    d.two_sided = jp.two_sided;
+    d.nest_cap = (int)nest_words(jp.k, jp.ell, jp.two_sided);
+    d.lcap = jp.lcap;
+    d.scstride = jp.k + 2;
+    d.nblocks = jp.nblocks;
+    d.precision = jp.precision;
+    return d;
+}
+
+OuterLaunch group_launch(const Plan& P, int gi, JobDesc* table) {
+    const auto [start, count] = P.groups[gi];
+    const JobPlan& jp = P.jobs[start];
+    OuterLaunch L{};
+    L.g = jp.lat->g;
+    L.links = jp.precision == NKS_FP64 ? (const void*)jp.lat->links64 : (const void*)jp.lat->links32;
+    L.kappa = jp.lat->kappa;
+    L.mu = jp.lat->mu;
+    L.jobs = table + start;
+    L.njobs = count;
+    L.kmax = 0;
+    for (int i = start; i < start + count; ++i) L.kmax = std::max(L.kmax, P.jobs[i].k);
+    L.nblocks = jp.nblocks;
+    L.precision = jp.precision;
+    L.two_sided = jp.two_sided;
+    return L;
+}
+
+constexpr int PROF_EVERY = 8;     // time one launch in eight of each class
+constexpr size_t PROF_POOL = 4096;
+
+// Begin timing a launch of class cls if it is sampled; returns the record index or -1.
+int prof_begin(nks_ctx* ctx, int cls, double bytes, hipStream_t s) {
+    if (!ctx->prof) return -1;
+    if (ctx->prof_count[cls]++ % PROF_EVERY != 0) return -1;
+    if (ctx->pool.size() < 2) return -1;
+    ProfRecord r{cls, ctx->pool.back(), nullptr, bytes};
+    ctx->pool.pop_back();
+    r.b = ctx->pool.back();
+    ctx->pool.pop_back();
+    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
+    ctx->pending.push_back(r);
+    return (int)ctx->pending.size() - 1;
+}
+void prof_end(nks_ctx* ctx, int rec, hipStream_t s) {
+    if (rec >= 0) (void)hipEventRecord(ctx->pending[rec].b, s);
+}
+
+// Algorithmic bytes of one launch: every input read once, every output written once.
+double bytes_S(const OuterLaunch& L, const Plan& P, int start, int j) {
+    const double cs = L.precision == NKS_FP64 ? 16.0 : 8.0;
+    const double sp = 12.0 * cs, lk = 36.0 * cs;
+    double per_site = lk;
+    for (int i = start; i < start + L.njobs; ++i) {
+        const int k = P.jobs[i].k;
+        if (j > k) continue;
+        const double f = L.two_sided ? 2.0 : 1.0;          // A v and A^dagger w
+        per_site += f * sp * (1.0 + (j >= 2 ? 1.0 : 0.0) + (j < k ? 1.0 : 0.0));
+    }
+    return per_site * L.g.V;
+}
+double bytes_R(const OuterLaunch& L, const Plan& P, int start, int j) {
+    const double cs = L.precision == NKS_FP64 ? 16.0 : 8.0;
+    const double sp = 12.0 * cs;
+    double per_site = 0.0;
+    for (int i = start; i < start + L.njobs; ++i)
+        if (j < P.jobs[i].k) per_site += (L.two_sided ? 6.0 : 3.0) * sp;
+    return per_site * L.g.V;
+}
+double bytes_lift(const OuterLaunch& L, const Plan& P, int start) {
+    const double cs = L.precision == NKS_FP64 ? 16.0 : 8.0;
+    double per_site = 0.0;
+    for (int i = start; i < start + L.njobs; ++i) per_site += 12.0 * cs * P.jobs[i].k + 12.0 * 16.0;
+    return per_site * L.g.V;
+}
+
+enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1 };
+
+// Enqueue the whole method for all jobs.  Events (if non-null) mark phase ends.
+int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s,
+            bool timed, int phase) {
+    JobDesc* table = reinterpret_cast<JobDesc*>(ws);
+    HIP_TRY(ctx, hipMemcpyAsync(table, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        OuterLaunch L = group_launch(P, (int)gi, table);
+        const int start = P.groups[gi].first;
+        launch_pack(L, s);
+        for (int j = 1; j <= L.kmax; ++j) {
+            int r = prof_begin(ctx, NKS_K_STENCIL, ctx->prof ? bytes_S(L, P, start, j) : 0.0, s);
+            launch_outer_S(L, j, s);
+            prof_end(ctx, r, s);
+            if (j < L.kmax) {
+                r = prof_begin(ctx, NKS_K_RECUR, ctx->prof ? bytes_R(L, P, start, j) : 0.0, s);
+                launch_outer_R(L, j, s);
+                prof_end(ctx, r, s);
+            }
+        }
+    }
+    launch_finalize(table, (int)descs.size(), s);
+    HIP_TRY(ctx, hipGetLastError());
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
+    if (phase == PH_OUTER_ONLY) return NKS_OK;
+    {
+        const long long c = ctx->prof_count[NKS_K_NESTED];
+        ctx->prof_count[NKS_K_NESTED] = 0;   // the nested launch is always timed when profiling
+        int r = prof_begin(ctx, NKS_K_NESTED, 0.0, s);
+        ctx->prof_count[NKS_K_NESTED] = c + 1;
+        launch_nested(table, (int)descs.size(), s);
+        prof_end(ctx, r, s);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        OuterLaunch L = group_launch(P, (int)gi, table);
+        const long long c = ctx->prof_count[NKS_K_LIFT];
+        ctx->prof_count[NKS_K_LIFT] = 0;
+        int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, s);
+        ctx->prof_count[NKS_K_LIFT] = c + 1;
+        launch_lift(L, s);
+        prof_end(ctx, r, s);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+    return NKS_OK;
+}
+
+int read_stats(nks_ctx* ctx, const Plan& P, char* ws, bool timed, nks_stats* out_by_caller_index) {
+    float t01 = 0, t12 = 0, t23 = 0;
+    if (timed) {
+        (void)hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+        (void)hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+        (void)hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+    }
+    for (const auto& jp : P.jobs) {
+        int st[ST_COUNT];
+        double rp[RP_COUNT];
+        HIP_TRY(ctx, hipMemcpy(st, ws + jp.off_status, sizeof(st), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpy(rp, ws + jp.off_report, sizeof(rp), hipMemcpyDeviceToHost));
+        nks_stats& o = out_by_caller_index[jp.idx];
+        std::memset(&o, 0, sizeof(o));
+        o.status = st[ST_STATUS];
+        o.k_used = st[ST_KUSED];
+        o.ell_used = st[ST_ELL];
+        o.rhi_iters = st[ST_RHI];
+        o.breakdown_iter = st[ST_BDITER];
+        o.p_used = rp[RP_P];
+        o.z_min = rp[RP_ZMIN];
+        o.z_max = rp[RP_ZMAX];
+        o.b_norm = rp[RP_BNORM];
+        o.inner_delta = rp[RP_INNER_DELTA];
+        o.outer_delta = rp[RP_OUTER_DELTA];
+        o.ms_outer = t01;
+        o.ms_nested = t12;
+        o.ms_lift = t23;
+    }
+    return NKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nks_opts_default(nks_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->size = sizeof(nks_opts);
+    o->k = 200;
+    o->ell = 50;
+    o->tol = 1e-8;
+    o->precision = NKS_FP64;
+    o->p = 0.0;
+    o->k_policy = NKS_POLICY_FIXED;
+    o->ell_policy = NKS_POLICY_FIXED;
+    o->max_rhi_iter = 50;
+    o->rhi_tol = 1e-14;
+    o->flags = 0;
+}
+
+int nks_create(int device, nks_ctx** out) {
+    if (!out) return NKS_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return NKS_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return NKS_E_HIP;
+    auto* c = new nks_ctx();
+    c->device = device;
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) { delete c; return NKS_E_HIP; }
+    *out = c;
+    return NKS_OK;
+}
+
+void nks_destroy(nks_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& r : ctx->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto& e : ctx->pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char* nks_last_error(nks_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+const char* nks_status_str(int s) {
+    switch (s) {
+        case NKS_OK: return "ok";
+        case NKS_E_INVALID: return "invalid argument";
+        case NKS_E_NOMEM: return "workspace too small or out of memory";
+        case NKS_E_HIP: return "HIP error";
+        case NKS_E_UNSUPPORTED: return "unsupported";
+        case NKS_E_BREAKDOWN: return "serious two-sided Lanczos breakdown";
+        case NKS_E_NOCONV: return "no convergence";
+        default: return "unknown status";
+    }
+}
+
+int nks_lattice_create(nks_ctx* ctx, const int32_t dims[4], const void* links_dev, nks_lattice** out) {
+    if (!ctx || !dims || !links_dev || !out) return fail(ctx, NKS_E_INVALID, "NULL argument");
+    *out = nullptr;
+    long long V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (dims[i] < 2) return fail(ctx, NKS_E_INVALID, "every lattice extent must be >= 2");
+        V *= dims[i];
+    }
+    if (V * 36 > (1LL << 31) - 1) return fail(ctx, NKS_E_UNSUPPORTED, "lattice too large for 32-bit indexing");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    auto lat = std::make_unique<nks_lattice>();
+    lat->ctx = ctx;
+    lat->g = Geom{dims[0], dims[1], dims[2], dims[3], (int)V};
+    HIP_TRY(ctx, hipMalloc(&lat->links64, sizeof(double2) * 36 * V));
+    HIP_TRY(ctx, hipMalloc(&lat->links32, sizeof(float2) * 36 * V));
+    HIP_TRY(ctx, hipMalloc(&lat->tmp, sizeof(double2) * 24 * V));
+    const int n = (int)(36 * V);
+    hipLaunchKernelGGL(links_to_soa, dim3((n + 255) / 256), dim3(256), 0, nullptr,
+                       static_cast<const double2*>(links_dev), lat->links64, lat->links32, (int)V);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    *out = lat.release();
+    return NKS_OK;
+}
+
+int nks_lattice_set_params(nks_lattice* lat, double m0, double mu) {
+    if (!lat) return NKS_E_INVALID;
+    const double mw = -m0;
+    if (!(mw > -2.0 && mw < 0.0)) return fail(lat->ctx, NKS_E_INVALID, "m_w = -m0 must lie in (-2, 0)");
+    if (!(mu == mu) || mu > 50.0 || mu < -50.0) return fail(lat->ctx, NKS_E_INVALID, "mu must be finite");
+    lat->m0 = m0;
+    lat->mu = mu;
+    lat->kappa = 1.0 / (8.0 + 2.0 * mw);
+    return NKS_OK;
+}
+
+void nks_lattice_destroy(nks_lattice* lat) {
+    if (!lat) return;
+    (void)hipFree(lat->links64);
+    (void)hipFree(lat->links32);
+    (void)hipFree(lat->tmp);
+    delete lat;
+}
+
+int nks_apply_op(nks_lattice* lat, const void* in, void* out, int dagger, int precision, void* stream) {
+    if (!lat || !in || !out) return fail(lat ? lat->ctx : nullptr, NKS_E_INVALID, "NULL argument");
+    if (in == out) return fail(lat->ctx, NKS_E_INVALID, "in and out must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double mu = dagger ? -lat->mu : lat->mu;
+    const size_t n = (size_t)12 * lat->g.V;
+    if (precision == NKS_FP64) {
+        launch_apply<double>(lat->g, lat->links64, lat->kappa, mu, static_cast<const double2*>(in),
+                             static_cast<double2*>(out), lat->tmp, lat->tmp + n, s);
+    } else if (precision == NKS_MIXED) {
+        auto* t = reinterpret_cast<float2*>(lat->tmp);
+        launch_apply<float>(lat->g, lat->links32, lat->kappa, mu, static_cast<const double2*>(in),
+                            static_cast<double2*>(out), t, t + n, s);
+    } else {
+        return fail(lat->ctx, NKS_E_INVALID, "unknown precision");
+    }
+    HIP_TRY(lat->ctx, hipGetLastError());
+    return NKS_OK;
+}
+
+int nks_workspace_size(nks_ctx* ctx, int njobs, const nks_job* jobs, size_t* bytes) {
+    if (!ctx || !bytes) return NKS_E_INVALID;
+    Plan P;
+    int rc = make_plan(ctx, njobs, jobs, P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return NKS_OK;
+}
+
+int nks_sign_apply_batch(nks_ctx* ctx, int njobs, const nks_job* jobs, void* ws, size_t ws_bytes, void* stream,
+                         nks_stats* stats) {
+    if (!ctx) return NKS_E_INVALID;
+    Plan P;
+    int rc = make_plan(ctx, njobs, jobs, P);
+    if (rc) return rc;
+    if (!ws || ws_bytes < P.total)
+        return fail(ctx, NKS_E_NOMEM, "workspace smaller than nks_workspace_size (" + std::to_string(P.total) + " bytes)");
+    for (int i = 0; i < njobs; ++i)
+        if (!jobs[i].b || !jobs[i].x) return fail(ctx, NKS_E_INVALID, "job b or x is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    char* w = static_cast<char*>(ws);
+    std::vector<JobDesc>& descs = ctx->descs;
+    descs.clear();
+    for (const auto& jp : P.jobs) descs.push_back(make_desc(jp, w, jobs[jp.idx].b, jobs[jp.idx].x));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool timed = stats != nullptr;
+    rc = enqueue(ctx, P, descs, w, s, timed, PH_ALL);
+    if (rc) return rc;
+    if (stats) {
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        rc = read_stats(ctx, P, w, timed, stats);
+        if (rc) return rc;
+    }
+    return NKS_OK;
+}
+
+int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x, const nks_opts* opts, void* ws,
+                   size_t ws_bytes, void* stream, nks_stats* stats) {
+    nks_job j{lat, b, x, opts};
+    return nks_sign_apply_batch(ctx, 1, &j, ws, ws_bytes, stream, stats);
+}
+
+int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opts* opts, void* ws, size_t ws_bytes,
+                    void* stream, double* alpha_host, double* beta_host, double* gamma_host, nks_stats* stats) {
+    if (!ctx || !lat || !b || !alpha_host || !beta_host || !gamma_host) return fail(ctx, NKS_E_INVALID, "NULL argument");
+    nks_job j{lat, b, nullptr, opts};
+    Plan P;
+    int rc = make_plan(ctx, 1, &j, P);
+    if (rc) return rc;
+    if (!ws || ws_bytes < P.total) return fail(ctx, NKS_E_NOMEM, "workspace too small");
+    char* w = static_cast<char*>(ws);
+    std::vector<JobDesc> descs{make_desc(P.jobs[0], w, b, nullptr)};
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = enqueue(ctx, P, descs, w, s, false, PH_OUTER_ONLY);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const JobPlan& jp = P.jobs[0];
+    int st[ST_COUNT];
+    HIP_TRY(ctx, hipMemcpy(st, w + jp.off_status, sizeof(st), hipMemcpyDeviceToHost));
+    const int k = st[ST_KUSED];
+    std::vector<double2> sc((size_t)SC_COUNT * (jp.k + 2));
+    HIP_TRY(ctx, hipMemcpy(sc.data(), w + jp.off_sc, sizeof(double2) * sc.size(), hipMemcpyDeviceToHost));
+    const size_t stride = jp.k + 2;
+    for (int i = 0; i < jp.k; ++i) {
+        double2 a = i < k ? sc[SC_ALPHA * stride + i + 1] : mk(0, 0);
+        alpha_host[2 * i] = a.x;
+        alpha_host[2 * i + 1] = a.y;
+        if (i + 1 < jp.k) {
+            double2 bb = i + 1 < k ? sc[SC_BETA * stride + i + 1] : mk(0, 0);
+            double2 gg = i + 1 < k ? sc[SC_GAMMA * stride + i + 1] : mk(0, 0);
+            beta_host[2 * i] = bb.x;
+            beta_host[2 * i + 1] = bb.y;
+            gamma_host[2 * i] = gg.x;
+            gamma_host[2 * i + 1] = gg.y;
+        }
+    }
+    if (stats) {
+        nks_stats tmp[1];
+        rc = read_stats(ctx, P, w, false, tmp);
+        if (rc) return rc;
+        *stats = tmp[0];
+    }
+    return NKS_OK;
+}
+
+int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double* beta_host, const double* gamma_host,
+                    int hermitian, const nks_opts* opts, double* c_host, nks_stats* stats) {
+    if (!ctx || !alpha_host || !c_host || (k > 1 && (!beta_host || !gamma_host)))
+        return fail(ctx, NKS_E_INVALID, "NULL argument");
+    if (k < 1) return fail(ctx, NKS_E_INVALID, "k must be >= 1");
+    int rc = validate_opts(ctx, opts);
+    if (rc) return rc;
+    const int ell = even_up(opts->ell);
+    if (ell >= k && k > NONNESTED_MAX) return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode limited to k <= 1024");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // a one-job layout: descriptor, scalars, status, report, omega, nest
+    const size_t stride = (size_t)k + 2;
+    const int lcap = ell >= k ? k : ell;
+    size_t off = align_up(sizeof(JobDesc));
+    const size_t off_sc = off; off = align_up(off + sizeof(double2) * SC_COUNT * stride);
+    const size_t off_st = off; off = align_up(off + sizeof(int) * ST_COUNT);
+    const size_t off_rp = off; off = align_up(off + sizeof(double) * RP_COUNT);
+    const size_t off_om = off; off = align_up(off + sizeof(double2) * k);
+    const size_t off_ne = off; off = align_up(off + sizeof(double2) * nest_words(k, ell, !hermitian));
+    char* w = nullptr;
+    HIP_TRY(ctx, hipMalloc(&w, off));
+    std::unique_ptr<char, decltype(&hipFree)> guard(w, &hipFree);
+    std::vector<double2> sc(SC_COUNT * stride, mk(0, 0));
+    for (int i = 0; i < k; ++i) {
+        sc[SC_ALPHA * stride + i + 1] = mk(alpha_host[2 * i], hermitian ? 0.0 : alpha_host[2 * i + 1]);
+        if (i + 1 < k) {
+            sc[SC_BETA * stride + i + 1] = mk(beta_host[2 * i], hermitian ? 0.0 : beta_host[2 * i + 1]);
+            sc[SC_GAMMA * stride + i + 1] =
+                hermitian ? sc[SC_BETA * stride + i + 1] : mk(gamma_host[2 * i], gamma_host[2 * i + 1]);
+        }
+        sc[SC_SV * stride + i + 1] = mk(1.0, 0.0);
+        sc[SC_SW * stride + i + 1] = mk(1.0, 0.0);
+    }
+    int st[ST_COUNT] = {0};
+    st[ST_DONE] = 1;
+    st[ST_KUSED] = k;
+    double rp[RP_COUNT] = {0};
+    rp[RP_BNORM] = 1.0;
+    JobDesc d{};
+    d.sc = reinterpret_cast<double2*>(w + off_sc);
+    d.status = reinterpret_cast<int*>(w + off_st);
+    d.report = reinterpret_cast<double*>(w + off_rp);
+    d.omega = reinterpret_cast<double2*>(w + off_om);
+    d.nest = reinterpret_cast<double2*>(w + off_ne);
+    d.k = k;
+    d.ell = ell;
+    d.p = opts->p;
+    d.max_rhi = opts->max_rhi_iter;
+    d.rhi_tol = opts->rhi_tol;
+    d.two_sided = !hermitian;
+    d.nest_cap = (int)nest_words(k, ell, !hermitian);
+    d.lcap = lcap;
+    d.scstride = (int)stride;
+    d.precision = NKS_FP64;
+    HIP_TRY(ctx, hipMemcpy(w, &d, sizeof(d), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(w + off_sc, sc.data(), sizeof(double2) * sc.size(), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(w + off_st, st, sizeof(st), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(w + off_rp, rp, sizeof(rp), hipMemcpyHostToDevice));
+    launch_nested(reinterpret_cast<JobDesc*>(w), 1, nullptr);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemcpy(c_host, w + off_om, sizeof(double2) * k, hipMemcpyDeviceToHost));
+    if (stats) {
+        HIP_TRY(ctx, hipMemcpy(st, w + off_st, sizeof(st), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpy(rp, w + off_rp, sizeof(rp), hipMemcpyDeviceToHost));
+        std::memset(stats, 0, sizeof(*stats));
+        stats->status = st[ST_STATUS];
+        stats->k_used = k;
+        stats->ell_used = st[ST_ELL];
+        stats->rhi_iters = st[ST_RHI];
+        stats->p_used = rp[RP_P];
+        stats->z_min = rp[RP_ZMIN];
+        stats->z_max = rp[RP_ZMAX];
+        stats->b_norm = 1.0;
+    }
+    return NKS_OK;
+}
+
+int nks_profile_enable(nks_ctx* ctx, int enable) {
+    if (!ctx) return NKS_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (enable && ctx->pool.empty() && ctx->pending.empty()) {
+        for (size_t i = 0; i < PROF_POOL; ++i) {
+            hipEvent_t e;
+            HIP_TRY(ctx, hipEventCreate(&e));
+            ctx->pool.push_back(e);
+        }
+    }
+    ctx->prof = enable != 0;
+    for (auto& c : ctx->prof_count) c = 0;
+    return NKS_OK;
+}
+
+int nks_profile_read(nks_ctx* ctx, int kernel_class, int* launches, double* total_ms, double* alg_bytes) {
+    if (!ctx || kernel_class < 0 || kernel_class >= NKS_K_COUNT || !launches || !total_ms || !alg_bytes)
+        return fail(ctx, NKS_E_INVALID, "bad nks_profile_read arguments");
+    int n = 0;
+    double ms = 0.0, bytes = 0.0;
+    std::vector<ProfRecord> keep;
+    for (auto& r : ctx->pending) {
+        if (r.cls != kernel_class) { keep.push_back(r); continue; }
+        HIP_TRY(ctx, hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&t, r.a, r.b));
+        ++n;
+        ms += t;
+        bytes += r.bytes;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->pending.swap(keep);
+    *launches = n;
+    *total_ms = ms;
+    *alg_bytes = bytes;
+    return NKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,801 @@
+// Nested step of the method (Sec. 4.1, App. C steps 3-5) on the device,
+// one workgroup per job:
+//
+//   3. p (given, or p_opt = (z_min z_max)^{-1/2} of Eq. popt from estimated
+//      Ritz-value extremes of H_k) and the LU of p H_k with row interchanges,
+//      exactly as LAPACK ?gttrf builds it;
+//   4. ell steps of Lanczos (mu = 0, real arithmetic) or two-sided Lanczos on
+//      H_k' = (p H_k + (p H_k)^{-1}) / 2 from e_1: (p H_k)^{-1} v by the LU
+//      back substitution (?gttrs, trans 'C' for the adjoint) plus the
+//      tridiagonal product p H_k v;
+//   5. Roberts-Higham iteration S <- (S + S^{-1}) / 2 (Eq. Roberts) on the
+//      dense ell x ell Ritz matrix, inverses by Gauss-Jordan with partial
+//      pivoting;
+//   then c = V_ell sgn(H_ell) e_1 and the lift weights omega_j = |b| c_j sv_j.
+//
+// With ell >= k_used the RHi runs on H_k itself (non-nested method).
+#include "nks_internal.h"
+
+namespace nks {
+
+namespace {
+
+constexpr int NT = NEST_NT;
+constexpr double RHI_NEAR = 1e-8;          // one more step once the change is below this
+constexpr double LUCKY_TAU_HERMITIAN = 1e-10;
+constexpr double LUCKY_TAU_TWO_SIDED = 1e-8;
+constexpr double SERIOUS_TAU = 1e-12;
+
+// ---- scalar helpers for T = double (real) or double2 (complex)
+__device__ inline double s_mul(double a, double b) { return a * b; }
+__device__ inline double2 s_mul(double2 a, double2 b) { return cmul(a, b); }
+__device__ inline double s_add(double a, double b) { return a + b; }
+__device__ inline double2 s_add(double2 a, double2 b) { return cadd(a, b); }
+__device__ inline double s_sub(double a, double b) { return a - b; }
+__device__ inline double2 s_sub(double2 a, double2 b) { return csub(a, b); }
+__device__ inline double s_div(double a, double b) { return a / b; }
+__device__ inline double2 s_div(double2 a, double2 b) { return cdiv(a, b); }
+__device__ inline double s_conj(double a) { return a; }
+__device__ inline double2 s_conj(double2 a) { return cconj(a); }
+__device__ inline double s_abs1(double a) { return fabs(a); }                 // LAPACK cabs1
+__device__ inline double s_abs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+__device__ inline double s_abs(double a) { return fabs(a); }
+__device__ inline double s_abs(double2 a) { return cabs(a); }
+__device__ inline double s_abs2(double a) { return a * a; }
+__device__ inline double s_abs2(double2 a) { return cabs2(a); }
+__device__ inline double s_scale(double a, double s) { return a * s; }
+__device__ inline double2 s_scale(double2 a, double s) { return cscale(a, s); }
+__device__ inline double2 s_d2(double a) { return mk(a, 0.0); }
+__device__ inline double2 s_d2(double2 a) { return a; }
+template <typename T> __device__ inline T s_from(double2 a);
+template <> __device__ inline double s_from<double>(double2 a) { return a.x; }
+template <> __device__ inline double2 s_from<double2>(double2 a) { return a; }
+template <typename T> __device__ inline T s_zero() { return s_from<T>(mk(0.0, 0.0)); }
+template <typename T> __device__ inline T s_one() { return s_from<T>(mk(1.0, 0.0)); }
+// conj(a) * b
+__device__ inline double s_dotterm(double a, double b) { return a * b; }
+__device__ inline double2 s_dotterm(double2 a, double2 b) { return cmulc(a, b); }
+__device__ inline double2 s_sqrt(double2 z) { return csqrt_principal(z); }
+
+// ---- block reductions of doubles
+__device__ inline double block_max(double v, double* lds) {
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = lds[0];
+    for (int w = 1; w < NT / 64; ++w) r = fmax(r, lds[w]);
+    return r;
+}
+__device__ inline double block_min(double v, double* lds) {
+    return -block_max(-v, lds);
+}
+// argmax of v with the smallest index on ties; returns the index
+__device__ inline int block_argmax(double v, int idx, double* ldsv, int* ldsi) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        double ov = __shfl_xor(v, m, 64);
+        int oi = __shfl_xor(idx, m, 64);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) { ldsv[threadIdx.x >> 6] = v; ldsi[threadIdx.x >> 6] = idx; }
+    __syncthreads();
+    double bv = ldsv[0];
+    int bi = ldsi[0];
+    for (int w = 1; w < NT / 64; ++w)
+        if (ldsv[w] > bv || (ldsv[w] == bv && ldsi[w] < bi)) { bv = ldsv[w]; bi = ldsi[w]; }
+    return bi;
+}
+
+template <typename T>
+__device__ inline T block_dot(const T* a, const T* b, int n, double2* lds) {   // sum conj(a) b
+    double2 s = mk(0.0, 0.0);
+    for (int i = threadIdx.x; i < n; i += NT) s = cadd(s, s_d2(s_dotterm(a[i], b[i])));
+    return s_from<T>(block_sum<NT>(s, lds));
+}
+template <typename T>
+__device__ inline double block_norm2(const T* a, int n, double2* lds) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) s += s_abs2(a[i]);
+    return block_sum<NT>(mk(s, 0.0), lds).x;
+}
+
+// ---- LAPACK-style tridiagonal LU with partial pivoting (serial, one thread)
+// dl: multipliers (n-1), d: U diagonal (n), du: first super-diagonal (n-1),
+// du2: second super-diagonal (n-2), ipiv: 0-based pivot rows.  Returns info.
+template <typename T>
+__device__ int gttrf(int n, T* dl, T* d, T* du, T* du2, int* ipiv) {
+    for (int i = 0; i < n; ++i) ipiv[i] = i;
+    for (int i = 0; i + 2 < n; ++i) du2[i] = s_zero<T>();
+    for (int i = 0; i + 1 < n; ++i) {
+        if (s_abs1(d[i]) >= s_abs1(dl[i])) {
+            if (s_abs1(d[i]) != 0.0) {
+                const T fact = s_div(dl[i], d[i]);
+                dl[i] = fact;
+                d[i + 1] = s_sub(d[i + 1], s_mul(fact, du[i]));
+            }
+        } else {
+            const T fact = s_div(d[i], dl[i]);
+            d[i] = dl[i];
+            dl[i] = fact;
+            const T temp = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = s_sub(temp, s_mul(fact, d[i + 1]));
+            if (i + 2 < n) {
+                du2[i] = du[i + 1];
+                du[i + 1] = s_scale(s_mul(fact, du[i + 1]), -1.0);
+            }
+            ipiv[i] = i + 1;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (s_abs1(d[i]) == 0.0) return i + 1;
+    return 0;
+}
+
+// ---- block-parallel solves with the LU factors of gttrf
+//
+// Every sweep of ?gttrs is a linear recurrence: the row interchanges of L
+// make the forward (and the L^H backward) sweep a first-order recurrence
+// c -> a c + b with |a| <= ~1, and U (U^H) with two super-diagonals is a
+// second-order one, s -> M s + g on s = (x_i, x_{i+1}).  Each thread composes
+// the affine maps of a contiguous chunk of steps, a Hillis-Steele scan over
+// the block gives every chunk its incoming state, and each thread replays
+// its chunk.  The arithmetic per step is the one of the serial sweep; only
+// the association of the chunk products differs.
+template <typename T> struct Aff1 { T a, b; };                   // c -> a c + b
+template <typename T> struct Aff2 { T m00, m01, m10, m11, g0, g1; };   // s -> M s + g
+
+template <typename T> __device__ inline Aff1<T> ident1() { return {s_one<T>(), s_zero<T>()}; }
+template <typename T> __device__ inline Aff2<T> ident2() {
+    return {s_one<T>(), s_zero<T>(), s_zero<T>(), s_one<T>(), s_zero<T>(), s_zero<T>()};
+}
+// later o earlier
+template <typename T> __device__ inline Aff1<T> compose(const Aff1<T>& l, const Aff1<T>& e) {
+    return {s_mul(l.a, e.a), s_add(s_mul(l.a, e.b), l.b)};
+}
+template <typename T> __device__ inline Aff2<T> compose(const Aff2<T>& l, const Aff2<T>& e) {
+    Aff2<T> r;
+    r.m00 = s_add(s_mul(l.m00, e.m00), s_mul(l.m01, e.m10));
+    r.m01 = s_add(s_mul(l.m00, e.m01), s_mul(l.m01, e.m11));
+    r.m10 = s_add(s_mul(l.m10, e.m00), s_mul(l.m11, e.m10));
+    r.m11 = s_add(s_mul(l.m10, e.m01), s_mul(l.m11, e.m11));
+    r.g0 = s_add(s_add(s_mul(l.m00, e.g0), s_mul(l.m01, e.g1)), l.g0);
+    r.g1 = s_add(s_add(s_mul(l.m10, e.g0), s_mul(l.m11, e.g1)), l.g1);
+    return r;
+}
+
+// Exclusive scan over scan positions 0..NT-1 (position pos composes after
+// positions < pos).  Returns the composition of all maps at positions < pos.
+template <typename Map>
+__device__ Map block_exclusive_scan(Map x, int pos, Map* lds, Map id) {
+    lds[pos] = x;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        Map y = x;
+        if (pos >= off) y = compose(x, lds[pos - off]);
+        __syncthreads();
+        lds[pos] = y;
+        x = y;
+        __syncthreads();
+    }
+    Map ex = (pos > 0) ? lds[pos - 1] : id;
+    __syncthreads();
+    return ex;
+}
+
+struct LUF {   // LU factors of p H_k (gttrf layout) in the nest area
+    const void *dl, *d, *du, *du2;
+    const int* ipiv;
+};
+
+// x = (L U)^{-1} P b   (LAPACK trans 'N');  b, t, x distinct; all threads
+template <typename T>
+__device__ void solve_n(const LUF& F, int n, const T* b, T* t, T* x, void* scan_lds) {
+    const T* dl = (const T*)F.dl;
+    const T* d = (const T*)F.d;
+    const T* du = (const T*)F.du;
+    const T* du2 = (const T*)F.du2;
+    const int tid = threadIdx.x;
+    const int steps = n - 1;
+    const int m = (steps + NT - 1) / NT;
+    const int i0 = tid * m, i1 = min(steps, i0 + m);
+    // forward sweep with interchanges: carry c_i = current b[i]
+    {
+        Aff1<T> f = ident1<T>();
+        for (int i = i0; i < i1; ++i) {
+            const T e = b[i + 1];
+            Aff1<T> st = (F.ipiv[i] == i) ? Aff1<T>{s_scale(dl[i], -1.0), e}
+                                          : Aff1<T>{s_one<T>(), s_scale(s_mul(dl[i], e), -1.0)};
+            f = compose(st, f);
+        }
+        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, tid, (Aff1<T>*)scan_lds, ident1<T>());
+        T c = s_add(s_mul(ex.a, b[0]), ex.b);
+        for (int i = i0; i < i1; ++i) {
+            const T e = b[i + 1];
+            if (F.ipiv[i] == i) { t[i] = c; c = s_sub(e, s_mul(dl[i], c)); }
+            else { t[i] = e; c = s_sub(c, s_mul(dl[i], e)); }
+        }
+        if (steps == 0 && tid == 0) t[0] = b[0];
+        else if (i1 == steps && i0 < i1) t[steps] = c;
+    }
+    __syncthreads();
+    // backward sweep with U: s_i = (x_i, x_{i+1}) = M_i s_{i+1} + g_i, i = n-2 .. 0
+    {
+        const int pos = NT - 1 - tid;   // later rows are composed first
+        Aff2<T> f = ident2<T>();
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            Aff2<T> st{s_scale(s_mul(du[i], inv), -1.0),
+                       (i + 2 < n) ? s_scale(s_mul(du2[i], inv), -1.0) : s_zero<T>(),
+                       s_one<T>(), s_zero<T>(), s_mul(t[i], inv), s_zero<T>()};
+            f = compose(st, f);
+        }
+        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, pos, (Aff2<T>*)scan_lds, ident2<T>());
+        const T xl = s_div(t[n - 1], d[n - 1]);
+        T s0 = s_add(s_mul(ex.m00, xl), ex.g0);
+        T s1 = s_add(s_mul(ex.m10, xl), ex.g1);
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            const T dd2 = (i + 2 < n) ? du2[i] : s_zero<T>();
+            const T xi = s_mul(s_sub(s_sub(t[i], s_mul(du[i], s0)), s_mul(dd2, s1)), inv);
+            s1 = s0;
+            s0 = xi;
+            x[i] = xi;
+        }
+        if (tid == 0) x[n - 1] = xl;
+    }
+    __syncthreads();
+}
+
+// x = ((L U)^H)^{-1} b   (LAPACK trans 'C');  b, t, x distinct; all threads
+template <typename T>
+__device__ void solve_c(const LUF& F, int n, const T* b, T* t, T* x, void* scan_lds) {
+    const T* dl = (const T*)F.dl;
+    const T* d = (const T*)F.d;
+    const T* du = (const T*)F.du;
+    const T* du2 = (const T*)F.du2;
+    const int tid = threadIdx.x;
+    const int steps = n - 1;
+    const int m = (steps + NT - 1) / NT;
+    const int i0 = 1 + tid * m, i1 = min(n, i0 + m);   // rows 1..n-1
+    // forward sweep with U^H: s_i = (x_i, x_{i-1}) = N_i s_{i-1} + h_i
+    {
+        Aff2<T> f = ident2<T>();
+        for (int i = i0; i < i1; ++i) {
+            const T inv = s_div(s_one<T>(), s_conj(d[i]));
+            Aff2<T> st{s_scale(s_mul(s_conj(du[i - 1]), inv), -1.0),
+                       (i >= 2) ? s_scale(s_mul(s_conj(du2[i - 2]), inv), -1.0) : s_zero<T>(),
+                       s_one<T>(), s_zero<T>(), s_mul(b[i], inv), s_zero<T>()};
+            f = compose(st, f);
+        }
+        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, tid, (Aff2<T>*)scan_lds, ident2<T>());
+        const T x0 = s_div(b[0], s_conj(d[0]));
+        T s0 = s_add(s_mul(ex.m00, x0), ex.g0);
+        T s1 = s_add(s_mul(ex.m10, x0), ex.g1);
+        for (int i = i0; i < i1; ++i) {
+            const T inv = s_div(s_one<T>(), s_conj(d[i]));
+            const T c2 = (i >= 2) ? s_conj(du2[i - 2]) : s_zero<T>();
+            const T xi = s_mul(s_sub(s_sub(b[i], s_mul(s_conj(du[i - 1]), s0)), s_mul(c2, s1)), inv);
+            s1 = s0;
+            s0 = xi;
+            t[i] = xi;
+        }
+        if (tid == 0) t[0] = x0;
+    }
+    __syncthreads();
+    // backward sweep with L^H and the interchanges: carry c, steps i = n-2 .. 0
+    {
+        const int pos = NT - 1 - tid;
+        const int j0 = tid * m, j1 = min(steps, j0 + m);   // steps j0..j1-1, run descending
+        Aff1<T> f = ident1<T>();
+        for (int i = j1 - 1; i >= j0; --i) {
+            Aff1<T> st = (F.ipiv[i] == i) ? Aff1<T>{s_scale(s_conj(dl[i]), -1.0), t[i]}
+                                          : Aff1<T>{s_one<T>(), s_zero<T>()};
+            f = compose(st, f);
+        }
+        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, pos, (Aff1<T>*)scan_lds, ident1<T>());
+        T c = s_add(s_mul(ex.a, t[n - 1]), ex.b);
+        for (int i = j1 - 1; i >= j0; --i) {
+            if (F.ipiv[i] == i) { x[i + 1] = c; c = s_sub(t[i], s_mul(s_conj(dl[i]), c)); }
+            else { x[i + 1] = s_sub(t[i], s_mul(s_conj(dl[i]), c)); }
+        }
+        if (steps == 0) { if (tid == 0) x[0] = t[0]; }
+        else if (j0 == 0 && j0 < j1) x[0] = c;
+    }
+    __syncthreads();
+}
+
+// ---- nest-area layout
+struct NestPtrs {
+    void *d, *sub, *sup;        // H_k diagonals (k)
+    void *lf, *u0, *u1, *u2;    // LU factors (k each)
+    int* piv;                   // k
+    void* vl;                   // inner basis, L columns of k
+    void *v, *vp, *w, *wp, *r, *l, *y, *t;   // work vectors (k)
+    void *al, *bl, *gl;         // H_ell (L)
+    void *S, *B;                // dense L x L
+    void *prow, *fcol;          // L
+    int* perm;                  // L
+};
+
+__host__ __device__ inline size_t nest_words_impl(int k, int L) {
+    // complex words (16 bytes); int arrays rounded up
+    return (size_t)3 * k + 4 * (size_t)k + ((size_t)k + 3) / 4 + (size_t)k * L + 8 * (size_t)k + 3 * (size_t)L +
+           2 * (size_t)L * L + 2 * (size_t)L + ((size_t)L + 3) / 4 + 8;
+}
+
+__device__ inline NestPtrs nest_ptrs(double2* base, int k, int L) {
+    NestPtrs P;
+    double2* q = base;
+    auto take = [&](size_t n) { double2* r = q; q += n; return (void*)r; };
+    P.d = take(k); P.sub = take(k); P.sup = take(k);
+    P.lf = take(k); P.u0 = take(k); P.u1 = take(k); P.u2 = take(k);
+    P.piv = (int*)take(((size_t)k + 3) / 4);
+    P.vl = take((size_t)k * L);
+    P.v = take(k); P.vp = take(k); P.w = take(k); P.wp = take(k); P.r = take(k); P.l = take(k); P.y = take(k);
+    P.t = take(k);
+    P.al = take(L); P.bl = take(L); P.gl = take(L);
+    P.S = take((size_t)L * L); P.B = take((size_t)L * L);
+    P.prow = take(L); P.fcol = take(L);
+    P.perm = (int*)take(((size_t)L + 3) / 4);
+    return P;
+}
+
+// y = 0.5 * ((pH)^{-1} v + p H v) (ADJ: with H^dagger); v, y length k; all threads
+template <typename T, bool ADJ>
+__device__ void apply_hprime(const NestPtrs& P, int k, double p, const T* v, T* y, void* scan_lds) {
+    const T* d = (const T*)P.d;
+    const T* sub = (const T*)P.sub;
+    const T* sup = (const T*)P.sup;
+    const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
+    if (!ADJ) solve_n<T>(F, k, v, (T*)P.t, y, scan_lds);
+    else solve_c<T>(F, k, v, (T*)P.t, y, scan_lds);
+    for (int i = threadIdx.x; i < k; i += NT) {
+        T hv;
+        if (!ADJ) {
+            hv = s_mul(d[i], v[i]);
+            if (i > 0) hv = s_add(hv, s_mul(sub[i - 1], v[i - 1]));
+            if (i + 1 < k) hv = s_add(hv, s_mul(sup[i], v[i + 1]));
+        } else {
+            hv = s_mul(s_conj(d[i]), v[i]);
+            if (i > 0) hv = s_add(hv, s_mul(s_conj(sup[i - 1]), v[i - 1]));
+            if (i + 1 < k) hv = s_add(hv, s_mul(s_conj(sub[i]), v[i + 1]));
+        }
+        y[i] = s_scale(s_add(y[i], s_scale(hv, p)), 0.5);
+    }
+    __syncthreads();
+}
+
+// Sturm count: number of eigenvalues < x of the real symmetric tridiagonal (d, e^2)
+__device__ inline int sturm_count(const double2* d, const double2* sub, int k, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0].x - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < k; ++i) {
+        const double e = sub[i - 1].x;
+        q = d[i].x - x - e * e / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// m-th smallest eigenvalue (1-based) by 256-way multisection of [-G, G]
+__device__ double find_eig(const double2* d, const double2* sub, int k, int m, double G, double pivmin,
+                           double* ldsd) {
+    double lo = -G, hi = G;
+    for (int round = 0; round < 4; ++round) {
+        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(NT + 1);
+        const int c = sturm_count(d, sub, k, x, pivmin);
+        const double cand_lo = (c < m) ? x : -INFINITY;
+        const double cand_hi = (c >= m) ? x : INFINITY;
+        const double nlo = block_max(cand_lo, ldsd);
+        const double nhi = block_min(cand_hi, ldsd);
+        if (nlo > lo) lo = nlo;
+        if (nhi < hi) hi = nhi;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Dense in-place inversion of the n x n row-major matrix B (Gauss-Jordan,
+// partial pivoting).  Returns false if a pivot is exactly zero.
+template <typename T>
+__device__ bool gj_invert(T* B, int n, T* prow, T* fcol, int* perm, double* ldsd, int* ldsi) {
+    bool ok = true;
+    for (int kk = 0; kk < n; ++kk) {
+        double best = -1.0;
+        int bidx = n;
+        for (int i = kk + threadIdx.x; i < n; i += NT) {
+            const double a = s_abs(B[(size_t)i * n + kk]);
+            if (a > best) { best = a; bidx = i; }
+        }
+        const int p = block_argmax(best, bidx, ldsd, ldsi);
+        if (threadIdx.x == 0) perm[kk] = p;
+        if (p != kk) {
+            for (int j = threadIdx.x; j < n; j += NT) {
+                const T t = B[(size_t)kk * n + j];
+                B[(size_t)kk * n + j] = B[(size_t)p * n + j];
+                B[(size_t)p * n + j] = t;
+            }
+        }
+        __syncthreads();
+        const T piv = B[(size_t)kk * n + kk];
+        if (s_abs1(piv) == 0.0) ok = false;
+        const T pivinv = s_div(s_one<T>(), piv);
+        for (int j = threadIdx.x; j < n; j += NT) prow[j] = (j == kk) ? pivinv : s_mul(B[(size_t)kk * n + j], pivinv);
+        for (int i = threadIdx.x; i < n; i += NT) fcol[i] = (i == kk) ? s_zero<T>() : B[(size_t)i * n + kk];
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += NT) {
+            const int i = e / n, j = e - i * n;
+            if (i == kk) B[e] = prow[j];
+            else B[e] = s_sub((j == kk) ? s_zero<T>() : B[e], s_mul(fcol[i], prow[j]));
+        }
+        __syncthreads();
+    }
+    for (int kk = n - 1; kk >= 0; --kk) {
+        const int p = perm[kk];
+        if (p != kk) {
+            for (int i = threadIdx.x; i < n; i += NT) {
+                const T t = B[(size_t)i * n + kk];
+                B[(size_t)i * n + kk] = B[(size_t)i * n + p];
+                B[(size_t)i * n + p] = t;
+            }
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// Roberts-Higham on the dense n x n matrix S (row-major); B is scratch.
+// Returns iterations (negative if not converged).
+template <typename T>
+__device__ int rhi(T* S, T* B, int n, int maxit, double tol, T* prow, T* fcol, int* perm, double2* lds,
+                   double* ldsd, int* ldsi) {
+    bool last = false;
+    for (int it = 1; it <= maxit; ++it) {
+        for (int e = threadIdx.x; e < n * n; e += NT) B[e] = S[e];
+        __syncthreads();
+        const bool ok = gj_invert<T>(B, n, prow, fcol, perm, ldsd, ldsi);
+        if (!ok) return -it;
+        double ch = 0.0, nm = 0.0;
+        for (int e = threadIdx.x; e < n * n; e += NT) {
+            const T sn = s_scale(s_add(S[e], B[e]), 0.5);
+            ch += s_abs2(s_sub(sn, S[e]));
+            nm += s_abs2(sn);
+            S[e] = sn;
+        }
+        const double2 r = block_sum<NT>(mk(ch, nm), lds);
+        const double change = sqrt(r.x) / sqrt(r.y);
+        if (change <= tol || last) return it;
+        if (change <= RHI_NEAR) last = true;
+    }
+    return -maxit;
+}
+
+template <typename T>
+__device__ void nested_job(const JobDesc& J, double2* lds, double* ldsd, int* ldsi, void* scan_lds) {
+    constexpr bool CPLX = sizeof(T) == sizeof(double2);
+    const int tid = threadIdx.x;
+    double2* sc = J.sc;
+    const size_t st = J.scstride;
+    double2* ALPHA = sc + SC_ALPHA * st;
+    double2* BETA = sc + SC_BETA * st;
+    double2* GAMMA = sc + SC_GAMMA * st;
+    double2* SV = sc + SC_SV * st;
+    double2* SW = sc + SC_SW * st;
+    const int kused = J.status[ST_KUSED];
+    if (kused == 0) return;                              // zero source; lift writes zeros
+    const int k = kused;
+    const double bnorm = J.report[RP_BNORM];
+    int ell = J.ell;
+    const bool nonnested = ell >= k;
+    const int L = nonnested ? k : ell;
+    NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
+    T* d = (T*)P.d;
+    T* sub = (T*)P.sub;
+    T* sup = (T*)P.sup;
+    for (int i = tid; i < k; i += NT) {
+        d[i] = s_from<T>(ALPHA[i + 1]);
+        if (i + 1 < k) { sub[i] = s_from<T>(BETA[i + 1]); sup[i] = s_from<T>(GAMMA[i + 1]); }
+    }
+    __syncthreads();
+    T* S = (T*)P.S;
+    T* B = (T*)P.B;
+    T* s_e1 = (T*)P.y;   // first column of sgn(H_ell)
+    int ell_used = 0, rhi_it = 0;
+    double p_used = 0.0, zmin = 0.0, zmax = 0.0;
+    T* vl = (T*)P.vl;
+    if (nonnested) {
+        for (int e = tid; e < k * k; e += NT) {
+            const int i = e / k, j = e - i * k;
+            T v = s_zero<T>();
+            if (i == j) v = d[i];
+            else if (i == j + 1) v = sub[j];
+            else if (j == i + 1) v = sup[i];
+            S[e] = v;
+        }
+        __syncthreads();
+        rhi_it = rhi<T>(S, B, k, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, lds, ldsd, ldsi);
+        __syncthreads();
+        for (int i = tid; i < k; i += NT) vl[i] = S[(size_t)i * k];   // c = S e_1
+        ell_used = 0;
+        __syncthreads();
+    } else {
+        // ---------------------------------------------------- step 3: p and LU
+        double p = J.p;
+        T* lf = (T*)P.lf;
+        T* u0 = (T*)P.u0;
+        T* u1 = (T*)P.u1;
+        T* u2 = (T*)P.u2;
+        if (p <= 0.0) {
+            if (!CPLX) {
+                // Ritz values of the real symmetric H_k by Sturm multisection
+                double g = 0.0;
+                const double2* dd = reinterpret_cast<const double2*>(ALPHA + 1);
+                const double2* ee = reinterpret_cast<const double2*>(BETA + 1);
+                double emax = 0.0;
+                for (int i = tid; i < k; i += NT) {
+                    const double el = (i > 0) ? fabs(ee[i - 1].x) : 0.0;
+                    const double er = (i + 1 < k) ? fabs(ee[i].x) : 0.0;
+                    g = fmax(g, fabs(dd[i].x) + el + er);
+                    emax = fmax(emax, er);
+                }
+                const double G = block_max(g, ldsd) * 1.001 + 1e-300;
+                const double em = block_max(emax, ldsd);
+                const double pivmin = 2.2250738585072014e-308 * fmax(1.0, em * em);
+                int c0;
+                {
+                    __shared__ int c0s;
+                    if (tid == 0) c0s = sturm_count(dd, ee, k, 0.0, pivmin);
+                    __syncthreads();
+                    c0 = c0s;
+                    __syncthreads();
+                }
+                const double l1 = find_eig(dd, ee, k, 1, G, pivmin, ldsd);
+                const double lk = find_eig(dd, ee, k, k, G, pivmin, ldsd);
+                zmax = fmax(fabs(l1), fabs(lk));
+                if (c0 == 0) zmin = fabs(l1);
+                else if (c0 == k) zmin = fabs(lk);
+                else {
+                    const double ln = find_eig(dd, ee, k, c0, G, pivmin, ldsd);
+                    const double lp = find_eig(dd, ee, k, c0 + 1, G, pivmin, ldsd);
+                    zmin = fmin(fabs(ln), fabs(lp));
+                }
+            } else {
+                // power iteration for z_max, inverse iteration (LU of H_k) for z_min;
+                // each estimate is the geometric mean of the per-step growth over
+                // the second half of the iterations, which damps the transient
+                // growth of a non-normal H_k
+                constexpr int NIT = 48, NAVG = 24;
+                T* x = (T*)P.v;
+                T* y = (T*)P.w;
+                for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+                __syncthreads();
+                double nx = sqrt(block_norm2<T>(x, k, lds));
+                for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
+                __syncthreads();
+                double lsum = 0.0;
+                for (int it = 0; it < NIT; ++it) {
+                    for (int i = tid; i < k; i += NT) {
+                        T hv = s_mul(d[i], x[i]);
+                        if (i > 0) hv = s_add(hv, s_mul(sub[i - 1], x[i - 1]));
+                        if (i + 1 < k) hv = s_add(hv, s_mul(sup[i], x[i + 1]));
+                        y[i] = hv;
+                    }
+                    __syncthreads();
+                    const double ny = sqrt(block_norm2<T>(y, k, lds));
+                    if (it >= NIT - NAVG) lsum += log(ny);
+                    for (int i = tid; i < k; i += NT) x[i] = s_scale(y[i], 1.0 / ny);
+                    __syncthreads();
+                }
+                zmax = exp(lsum / NAVG);
+                for (int i = tid; i < k; i += NT) {
+                    u0[i] = d[i];
+                    if (i + 1 < k) { lf[i] = sub[i]; u1[i] = sup[i]; }
+                }
+                __syncthreads();
+                __shared__ int info0;
+                if (tid == 0) info0 = gttrf<T>(k, lf, u0, u1, u2, P.piv);
+                __syncthreads();
+                for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+                __syncthreads();
+                if (info0 == 0) {
+                    const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
+                    lsum = 0.0;
+                    nx = sqrt(block_norm2<T>(x, k, lds));
+                    for (int it = 0; it < NIT; ++it) {
+                        for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
+                        __syncthreads();
+                        solve_n<T>(F, k, x, (T*)P.t, y, scan_lds);
+                        nx = sqrt(block_norm2<T>(y, k, lds));
+                        if (it >= NIT - NAVG) lsum += log(nx);
+                        T* sw_ = x; x = y; y = sw_;
+                    }
+                    zmin = exp(-lsum / NAVG);
+                } else {
+                    zmin = zmax * 1e-3;
+                }
+                __syncthreads();
+            }
+            p = 1.0 / sqrt(zmin * zmax);
+        }
+        p_used = p;
+        for (int i = tid; i < k; i += NT) {
+            u0[i] = s_scale(d[i], p);
+            if (i + 1 < k) { lf[i] = s_scale(sub[i], p); u1[i] = s_scale(sup[i], p); }
+        }
+        __syncthreads();
+        __shared__ int info;
+        if (tid == 0) info = gttrf<T>(k, lf, u0, u1, u2, P.piv);
+        __syncthreads();
+        if (info != 0) {
+            if (tid == 0) J.status[ST_STATUS] = NKS_E_NOCONV;
+            for (int i = tid; i < k; i += NT) J.omega[i] = mk(0.0, 0.0);
+            return;
+        }
+        // ---------------------------------------------------- step 4: inner Krylov space
+        T* v = (T*)P.v;
+        T* vp = (T*)P.vp;
+        T* w = (T*)P.w;
+        T* wp = (T*)P.wp;
+        T* r = (T*)P.r;
+        T* l = (T*)P.l;
+        T* al = (T*)P.al;
+        T* bl = (T*)P.bl;
+        T* gl = (T*)P.gl;
+        for (int i = tid; i < k; i += NT) {
+            v[i] = (i == 0) ? s_one<T>() : s_zero<T>();
+            vp[i] = s_zero<T>();
+            if (CPLX) { w[i] = v[i]; wp[i] = s_zero<T>(); }
+        }
+        __syncthreads();
+        apply_hprime<T, false>(P, k, p, v, r, scan_lds);
+        if (CPLX) apply_hprime<T, true>(P, k, p, w, l, scan_lds);
+        double vn = 1.0, wn = 1.0;
+        ell_used = L;
+        for (int i = 1; i <= L; ++i) {
+            for (int q = tid; q < k; q += NT) vl[(size_t)(i - 1) * k + q] = v[q];
+            __syncthreads();
+            if (!CPLX) {
+                const double a = s_d2(block_dot<T>(v, r, k, lds)).x;
+                if (tid == 0) al[i - 1] = s_from<T>(mk(a, 0.0));
+                for (int q = tid; q < k; q += NT) r[q] = s_sub(r[q], s_scale(v[q], a));
+                __syncthreads();
+                if (i == L) break;
+                const double b = sqrt(block_norm2<T>(r, k, lds));
+                const double bprev = (i >= 2) ? s_d2(bl[i - 2]).x : 0.0;
+                if (b <= LUCKY_TAU_HERMITIAN * (fabs(a) + bprev)) { ell_used = i; break; }
+                if (tid == 0) { bl[i - 1] = s_from<T>(mk(b, 0.0)); gl[i - 1] = bl[i - 1]; }
+                for (int q = tid; q < k; q += NT) {
+                    vp[q] = v[q];
+                    v[q] = s_scale(r[q], 1.0 / b);
+                }
+                __syncthreads();
+                apply_hprime<T, false>(P, k, p, v, r, scan_lds);
+                for (int q = tid; q < k; q += NT) r[q] = s_sub(r[q], s_scale(vp[q], b));
+                __syncthreads();
+            } else {
+                const double2 a = s_d2(block_dot<T>(w, r, k, lds));
+                if (tid == 0) al[i - 1] = s_from<T>(a);
+                for (int q = tid; q < k; q += NT) {
+                    r[q] = s_sub(r[q], s_mul(s_from<T>(a), v[q]));
+                    l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(a)), w[q]));
+                }
+                __syncthreads();
+                if (i == L) break;
+                const double2 delta = s_d2(block_dot<T>(r, l, k, lds));
+                const double nr = sqrt(block_norm2<T>(r, k, lds));
+                const double nl = sqrt(block_norm2<T>(l, k, lds));
+                const double S_ = cabs(a) + ((i >= 2) ? sqrt(cabs(cmul(s_d2(bl[i - 2]), s_d2(gl[i - 2])))) : 0.0);
+                if (nr <= LUCKY_TAU_TWO_SIDED * S_ * vn || nl <= LUCKY_TAU_TWO_SIDED * S_ * wn) {
+                    ell_used = i;
+                    break;
+                }
+                if (cabs(delta) <= SERIOUS_TAU * nr * nl) {
+                    ell_used = i;
+                    if (tid == 0) J.status[ST_STATUS] = NKS_E_BREAKDOWN;
+                    break;
+                }
+                const double2 beta = csqrt_principal(delta);
+                const double2 gamma = cdiv(cconj(delta), beta);
+                if (tid == 0) { bl[i - 1] = s_from<T>(beta); gl[i - 1] = s_from<T>(gamma); }
+                const double2 ib = crecip(beta), ig = crecip(cconj(gamma));
+                for (int q = tid; q < k; q += NT) {
+                    vp[q] = v[q];
+                    wp[q] = w[q];
+                    v[q] = s_mul(r[q], s_from<T>(ib));
+                    w[q] = s_mul(l[q], s_from<T>(ig));
+                }
+                vn = nr / cabs(beta);
+                wn = nl / cabs(gamma);
+                __syncthreads();
+                apply_hprime<T, false>(P, k, p, v, r, scan_lds);
+                apply_hprime<T, true>(P, k, p, w, l, scan_lds);
+                for (int q = tid; q < k; q += NT) {
+                    r[q] = s_sub(r[q], s_mul(s_from<T>(gamma), vp[q]));
+                    l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(beta)), wp[q]));
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+        // ---------------------------------------------------- step 5: RHi on H_ell
+        const int n = ell_used;
+        for (int e = tid; e < n * n; e += NT) {
+            const int i = e / n, j = e - i * n;
+            T val = s_zero<T>();
+            if (i == j) val = al[i];
+            else if (i == j + 1) val = bl[j];
+            else if (j == i + 1) val = gl[i];
+            S[e] = val;
+        }
+        __syncthreads();
+        rhi_it = rhi<T>(S, B, n, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, lds, ldsd, ldsi);
+        __syncthreads();
+        for (int j = tid; j < n; j += NT) s_e1[j] = S[(size_t)j * n];
+        __syncthreads();
+        // c = V_ell s  (into v)
+        T* c = (T*)P.v;
+        for (int q = tid; q < k; q += NT) {
+            T acc = s_zero<T>();
+            for (int j = 0; j < n; ++j) acc = s_add(acc, s_mul(vl[(size_t)j * k + q], s_e1[j]));
+            c[q] = acc;
+        }
+        __syncthreads();
+        for (int q = tid; q < k; q += NT) vl[q] = c[q];
+        __syncthreads();
+    }
+    // lift weights omega_j = |b| c_j sv_j (c in vl[0..k))
+    for (int q = tid; q < k; q += NT) J.omega[q] = cscale(cmul(s_d2(vl[q]), SV[q + 1]), bnorm);
+    if (tid == 0) {
+        if (rhi_it < 0 && J.status[ST_STATUS] == NKS_OK) J.status[ST_STATUS] = NKS_E_NOCONV;
+        J.status[ST_ELL] = ell_used;
+        J.status[ST_RHI] = rhi_it < 0 ? -rhi_it : rhi_it;
+        J.report[RP_P] = p_used;
+        J.report[RP_ZMIN] = zmin;
+        J.report[RP_ZMAX] = zmax;
+    }
+}
+
+__global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs) {
+    __shared__ double2 lds[NT / 64];
+    __shared__ double ldsd[NT / 64];
+    __shared__ int ldsi[NT / 64];
+    __shared__ Aff2<double2> scan_lds[NT];
+    const JobDesc& J = jobs[blockIdx.x];
+    if (J.two_sided) nested_job<double2>(J, lds, ldsd, ldsi, scan_lds);
+    else nested_job<double>(J, lds, ldsd, ldsi, scan_lds);
+}
+
+// H(k,k) = alpha_k from the partial sums of the last stencil pass (the
+// recurrence pass of iteration k is not needed: App. A/B stop after it).
+__global__ __launch_bounds__(NT) void finalize_kernel(JobDesc* jobs) {
+    __shared__ double2 lds[NT / 64];
+    const JobDesc& J = jobs[blockIdx.x];
+    const int kused = J.status[ST_KUSED];
+    if (kused == 0 || J.status[ST_DONE]) return;
+    const size_t st = J.scstride;
+    const double2 s = sum_partials<NT>(J.part + (size_t)PS_S * J.nblocks, J.nblocks, lds);
+    const double2 a = J.two_sided ? cmul(cconj(J.sc[SC_SW * st + kused]), s)
+                                  : mk(J.sc[SC_SV * st + kused].x * s.x, 0.0);
+    if (threadIdx.x == 0) J.sc[SC_ALPHA * st + kused] = a;
+}
+
+}  // namespace
+
+size_t nest_words(int k, int ell, int /*two_sided*/) {
+    const int L = ell >= k ? k : ell;
+    return nest_words_impl(k, L);
+}
+
+void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(njobs), dim3(NT), 0, s, jobs);
+}
+
+void launch_nested(JobDesc* jobs, int njobs, hipStream_t s) {
+    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs);
+}
+
+}  // namespace nks

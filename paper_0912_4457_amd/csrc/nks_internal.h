@@ -1,0 +1,194 @@
+// Internal definitions of libnks: device data layout, job descriptors,
+// complex helpers and block reductions shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/nks.h"
+
+namespace nks {
+
+// ----------------------------------------------------------------- complex
+template <typename R> struct cx;
+template <> struct cx<double> { using T = double2; };
+template <> struct cx<float> { using T = float2; };
+template <typename R> using cx_t = typename cx<R>::T;
+
+__host__ __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
+__host__ __device__ inline float2 mkf(float a, float b) { return make_float2(a, b); }
+
+template <typename V> __host__ __device__ inline V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __host__ __device__ inline V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __host__ __device__ inline V cmul(V a, V b) {
+    V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// conj(a) * b
+template <typename V> __host__ __device__ inline V cmulc(V a, V b) {
+    V r; r.x = a.x * b.x + a.y * b.y; r.y = a.x * b.y - a.y * b.x; return r;
+}
+template <typename V> __host__ __device__ inline V cconj(V a) { V r; r.x = a.x; r.y = -a.y; return r; }
+template <typename V, typename S> __host__ __device__ inline V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+// i * a and -i * a
+template <typename V> __host__ __device__ inline V cmuli(V a) { V r; r.x = -a.y; r.y = a.x; return r; }
+template <typename V> __host__ __device__ inline V cmulmi(V a) { V r; r.x = a.y; r.y = -a.x; return r; }
+template <typename V> __host__ __device__ inline V cneg(V a) { V r; r.x = -a.x; r.y = -a.y; return r; }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double cabs(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+    // a / b, scaled to avoid overflow in |b|^2
+    double s = fabs(b.x) > fabs(b.y) ? fabs(b.x) : fabs(b.y);
+    if (s == 0.0) return mk(a.x / 0.0, a.y / 0.0);
+    double bx = b.x / s, by = b.y / s;
+    double d = bx * bx + by * by;
+    double ax = a.x / s, ay = a.y / s;
+    return mk((ax * bx + ay * by) / d, (ay * bx - ax * by) / d);
+}
+__host__ __device__ inline double2 crecip(double2 b) { return cdiv(mk(1.0, 0.0), b); }
+// principal square root (branch cut on the negative real axis)
+__host__ __device__ inline double2 csqrt_principal(double2 z) {
+    double r = sqrt(z.x * z.x + z.y * z.y);
+    if (r == 0.0) return mk(0.0, 0.0);
+    double a = sqrt(0.5 * (r + fabs(z.x)));
+    double b = 0.5 * z.y / a;
+    if (z.x >= 0.0) return mk(a, b);
+    // z.x < 0: sqrt = (|b|, sign(y) a)
+    double im = (z.y >= 0.0) ? a : -a;
+    return mk(fabs(b), im);
+}
+
+template <typename R> __device__ inline double2 to_d2(cx_t<R> a) { return mk((double)a.x, (double)a.y); }
+template <typename R> __device__ inline cx_t<R> from_d2(double2 a);
+template <> __device__ inline double2 from_d2<double>(double2 a) { return a; }
+template <> __device__ inline float2 from_d2<float>(double2 a) { return mkf((float)a.x, (float)a.y); }
+
+// ----------------------------------------------------------------- geometry
+struct Geom {
+    int lx, ly, lz, lt;
+    int V;
+};
+
+// ----------------------------------------------------------------- jobs
+// Scalar slots of one job (each an array of double2 of length kcap + 2).
+enum ScalarSlot {
+    SC_ALPHA = 0,   // H(j,j), j = 1..k
+    SC_BETA = 1,    // H(j+1,j), j = 1..k-1
+    SC_GAMMA = 2,   // H(j,j+1), j = 1..k-1
+    SC_SV = 3,      // v_j = sv_j u_j (u_j: stored unnormalised vector)
+    SC_SW = 4,      // w_j = sw_j t_j
+    SC_VN = 5,      // ||v_j||
+    SC_WN = 6,      // ||w_j||
+    SC_COUNT = 7
+};
+
+// status words of one job
+enum StatusWord {
+    ST_DONE = 0,        // outer loop ended early (breakdown or zero source)
+    ST_KUSED = 1,       // outer basis size built
+    ST_STATUS = 2,      // NKS_OK / NKS_E_BREAKDOWN / NKS_E_NOCONV
+    ST_BDITER = 3,      // serious breakdown iteration
+    ST_ELL = 4,         // inner size used (0 = non-nested)
+    ST_RHI = 5,         // RHi iterations
+    ST_COUNT = 16
+};
+
+// doubles reported by the nested step
+enum ReportWord {
+    RP_BNORM = 0,
+    RP_P = 1,
+    RP_ZMIN = 2,
+    RP_ZMAX = 3,
+    RP_INNER_DELTA = 4,
+    RP_OUTER_DELTA = 5,
+    RP_COUNT = 8
+};
+
+// Partial-sum slots (each an array of double2 of length nblocks).
+enum PartialSlot { PS_S = 0, PS_R0 = 1, PS_R1 = 2, PS_R2 = 3, PS_COUNT = 4 };
+
+// One sign application, as seen by the device.  Lives in the workspace.
+struct JobDesc {
+    const double2* b;   // caller input, AoS complex128 (12*site + comp)
+    double2* x;         // caller output, AoS complex128
+    void* vstore;       // outer basis, (kcap + 1) columns of 12V storage-type complex, SoA
+    void* lring;        // two-sided left vectors, 2 columns of 12V
+    double2* part;      // PS_COUNT * nblocks partial sums
+    double2* sc;        // SC_COUNT * (kcap + 2) scalars
+    int* status;        // ST_COUNT ints
+    double* report;     // RP_COUNT doubles
+    double2* omega;     // lift weights, kcap
+    double2* nest;      // nested-step scratch
+    int k;              // requested outer size (even)
+    int ell;            // requested inner size (even)
+    double p;           // <= 0: estimate
+    int max_rhi;
+    double rhi_tol;
+    int two_sided;
+    int nest_cap;       // complex words available in nest
+    int lcap;           // inner size capacity of the nest area
+    int scstride;       // length of each scalar slot (kcap + 2)
+    int nblocks;        // blocks per job of the outer site-parallel kernels
+    int precision;      // NKS_FP64 / NKS_MIXED
+};
+
+// ----------------------------------------------------------------- reductions
+__device__ inline double2 shfl_xor_d2(double2 v, int m) {
+    v.x = __shfl_xor(v.x, m, 64);
+    v.y = __shfl_xor(v.y, m, 64);
+    return v;
+}
+
+// Sum over the block; result valid in every thread.  lds: >= NT/64 entries.
+template <int NT>
+__device__ inline double2 block_sum(double2 v, double2* lds) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = cadd(v, shfl_xor_d2(v, m));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double2 s = lds[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) s = cadd(s, lds[w]);
+    return s;
+}
+
+// Deterministic sum of n partials (same order in every block).
+template <int NT>
+__device__ inline double2 sum_partials(const double2* part, int n, double2* lds) {
+    double2 s = mk(0.0, 0.0);
+    for (int i = threadIdx.x; i < n; i += NT) s = cadd(s, part[i]);
+    return block_sum<NT>(s, lds);
+}
+
+// ----------------------------------------------------------------- launchers
+// wilson.hip
+template <typename R>
+void launch_apply(const Geom& g, const cx_t<R>* links, double kappa, double mu, const double2* in,
+                  double2* out, cx_t<R>* tmp_in, cx_t<R>* tmp_out, hipStream_t s);
+
+// outer.hip
+struct OuterLaunch {
+    Geom g;
+    const void* links;    // storage-type links, SoA [nu][row][col][V]
+    double kappa, mu;
+    JobDesc* jobs;        // device array
+    int njobs;
+    int kmax;             // max over jobs of k
+    int nblocks;          // blocks per job of the site-parallel kernels
+    int precision;        // NKS_FP64 / NKS_MIXED
+    int two_sided;
+};
+constexpr int OUTER_NT = 128;
+void launch_pack(const OuterLaunch& L, hipStream_t s);
+void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s);   // stencil pass of iteration j
+void launch_outer_R(const OuterLaunch& L, int j, hipStream_t s);   // recurrence pass (j < k only)
+void launch_lift(const OuterLaunch& L, hipStream_t s);
+
+// nested.hip
+constexpr int NEST_NT = 256;
+void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s);
+void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
+size_t nest_words(int k, int ell, int two_sided);
+
+}  // namespace nks

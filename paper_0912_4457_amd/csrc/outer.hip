@@ -1,0 +1,359 @@
+// Outer Krylov basis: Lanczos (App. A, mu = 0) and two-sided Lanczos
+// (App. B, mu != 0) with the Wilson stencil fused into the recurrences, and
+// the lift y = |b| V_k c of Eq. nested.
+//
+// The basis is stored unnormalised: column j of the store holds u_j with
+// v_j = sv_j u_j (sv_1 = 1/|b|, sv_{j+1} = 1/beta_j), so no pass is spent on
+// rescaling.  Per outer iteration j two site-parallel kernels run:
+//
+//   S_j (stencil):  r = sv_j A u_j - H(j-1,j) v_{j-1}           -> column j+1
+//                   [two-sided also l = sw_j A^dag t_j - conj(H(j,j-1)) w_{j-1}]
+//                   partial sums of conj(t_j) . r  (alpha_j / sv_j or / conj(sw_j))
+//   R_j (recurrence): alpha_j; r -= alpha_j v_j [l -= conj(alpha_j) w_j];
+//                   partial sums of |r|^2 [and r^dag l, |l|^2]
+//
+// Every block of S_{j+1} sums R_j's partials in the same order, so all blocks
+// agree on beta_j (and on a breakdown) without a grid barrier; block 0 stores
+// the scalars for the nested step.  All scalars stay on the device.
+#include "wilson.h"
+
+namespace nks {
+
+namespace {
+
+constexpr int NT = OUTER_NT;
+constexpr double LUCKY_TAU_HERMITIAN = 1e-10;
+constexpr double LUCKY_TAU_TWO_SIDED = 1e-8;
+constexpr double SERIOUS_TAU = 1e-12;
+
+__device__ inline double2* slot(const JobDesc& J, int s) { return J.sc + (size_t)s * J.scstride; }
+
+template <typename R>
+__device__ inline cx_t<R>* column(const JobDesc& J, int j, int n) {   // j is 1-based
+    return reinterpret_cast<cx_t<R>*>(J.vstore) + (size_t)(j - 1) * n;
+}
+
+template <typename R>
+__device__ inline cx_t<R>* lvec(const JobDesc& J, int j, int n) {     // t_j in ring slot j % 2
+    return reinterpret_cast<cx_t<R>*>(J.lring) + (size_t)(j & 1) * n;
+}
+
+// ------------------------------------------------------------------ pack
+template <typename R>
+__global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    __shared__ double2 lds[NT / 64];
+    const int site = blockIdx.x * NT + threadIdx.x;
+    const int n = 12 * V;
+    if (blockIdx.x == 0 && threadIdx.x < ST_COUNT) {
+        int v = 0;
+        if (threadIdx.x == ST_KUSED) v = J.k;
+        J.status[threadIdx.x] = v;
+    }
+    double nb2 = 0.0;
+    if (site < V) {
+        cx_t<R>* u1 = column<R>(J, 1, n);
+        cx_t<R>* t1 = J.two_sided ? lvec<R>(J, 1, n) : nullptr;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cx_t<R> v = from_d2<R>(J.b[(size_t)12 * site + c]);
+            u1[(size_t)c * V + site] = v;
+            if (t1) t1[(size_t)c * V + site] = v;
+            double2 d = to_d2<R>(v);
+            nb2 += cabs2(d);
+        }
+    }
+    double2 s = block_sum<NT>(mk(nb2, 0.0), lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------------ Hermitian step
+template <typename R>
+__global__ __launch_bounds__(NT) void herm_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
+                                            double kappa, int j, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (j > J.k || J.status[ST_DONE]) return;
+    __shared__ double2 lds[NT / 64];
+    const int n = 12 * g.V;
+    const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
+    // beta_{j-1} (or |b| when j == 1) from the previous kernel's partial sums
+    const double beta = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
+    double svj, cprev;
+    if (j == 1) {
+        if (beta == 0.0) {                                  // zero source: x = 0
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
+            return;
+        }
+        svj = 1.0 / beta;
+        cprev = 0.0;
+        if (b0) { J.report[RP_BNORM] = beta; slot(J, SC_SV)[1] = mk(svj, 0.0); slot(J, SC_VN)[1] = mk(1.0, 0.0); }
+    } else {
+        const double aprev = slot(J, SC_ALPHA)[j - 1].x;
+        const double bprev = (j >= 3) ? slot(J, SC_BETA)[j - 2].x : 0.0;
+        if (beta <= LUCKY_TAU_HERMITIAN * (fabs(aprev) + bprev)) {   // invariant subspace
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
+            return;
+        }
+        svj = 1.0 / beta;
+        cprev = beta * slot(J, SC_SV)[j - 1].x;                       // beta_{j-1} v_{j-1} = cprev u_{j-1}
+        if (b0) {
+            slot(J, SC_BETA)[j - 1] = mk(beta, 0.0);
+            slot(J, SC_GAMMA)[j - 1] = mk(beta, 0.0);
+            slot(J, SC_SV)[j] = mk(svj, 0.0);
+            slot(J, SC_VN)[j] = mk(1.0, 0.0);
+        }
+    }
+    const int site = blockIdx.x * NT + threadIdx.x;
+    double part = 0.0;
+    if (site < g.V) {
+        const cx_t<R>* uj = column<R>(J, j, n);
+        R cf[1][4], cb[1][4];
+        hop_coefs<R>(kappa, 0.0, cf[0], cb[0]);
+        const cx_t<R>* const fields[1] = {uj};
+        cx_t<R> acc[1][12];
+        wilson_site<R, 1>(g, links, fields, cf, cb, site, acc);
+        const cx_t<R>* up = (j >= 2) ? column<R>(J, j - 1, n) : nullptr;
+        cx_t<R>* rout = (j < J.k) ? column<R>(J, j + 1, n) : nullptr;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const size_t e = (size_t)c * g.V + site;
+            double2 r = cscale(to_d2<R>(acc[0][c]), svj);
+            if (up) r = csub(r, cscale(to_d2<R>(up[e]), cprev));
+            cx_t<R> rs = from_d2<R>(r);
+            if (rout) rout[e] = rs;
+            const double2 rd = to_d2<R>(rs);
+            const double2 u = to_d2<R>(uj[e]);
+            part += u.x * rd.x + u.y * rd.y;                          // Re(conj(u_j) r)
+        }
+    }
+    const double2 s = block_sum<NT>(mk(part, 0.0), lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (j >= J.k || J.status[ST_DONE]) return;
+    __shared__ double2 lds[NT / 64];
+    const int n = 12 * V;
+    const double svj = slot(J, SC_SV)[j].x;
+    const double alpha = svj * sum_partials<NT>(J.part + (size_t)PS_S * nblocks, nblocks, lds).x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = mk(alpha, 0.0);
+    const double cu = alpha * svj;
+    const int site = blockIdx.x * NT + threadIdx.x;
+    double nr2 = 0.0;
+    if (site < V) {
+        const cx_t<R>* uj = column<R>(J, j, n);
+        cx_t<R>* r = column<R>(J, j + 1, n);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const size_t e = (size_t)c * V + site;
+            double2 v = csub(to_d2<R>(r[e]), cscale(to_d2<R>(uj[e]), cu));
+            cx_t<R> vs = from_d2<R>(v);
+            r[e] = vs;
+            nr2 += cabs2(to_d2<R>(vs));
+        }
+    }
+    const double2 s = block_sum<NT>(mk(nr2, 0.0), lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------------ two-sided step
+template <typename R>
+__global__ __launch_bounds__(NT) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
+                                          double kappa, double mu, int j, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (j > J.k || J.status[ST_DONE]) return;
+    __shared__ double2 lds[NT / 64];
+    const int n = 12 * g.V;
+    const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
+    double2 sv, sw, cv, cw;   // v_j = sv u_j, w_j = sw t_j; subtract cv u_{j-1}, cw t_{j-1}
+    if (j == 1) {
+        const double bn = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
+        if (bn == 0.0) {
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
+            return;
+        }
+        sv = sw = mk(1.0 / bn, 0.0);
+        cv = cw = mk(0.0, 0.0);
+        if (b0) {
+            J.report[RP_BNORM] = bn;
+            slot(J, SC_SV)[1] = sv; slot(J, SC_SW)[1] = sw;
+            slot(J, SC_VN)[1] = mk(1.0, 0.0); slot(J, SC_WN)[1] = mk(1.0, 0.0);
+        }
+    } else {
+        const double2 delta = sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds);
+        const double nr = sqrt(sum_partials<NT>(J.part + (size_t)PS_R1 * nblocks, nblocks, lds).x);
+        const double nl = sqrt(sum_partials<NT>(J.part + (size_t)PS_R2 * nblocks, nblocks, lds).x);
+        const double aprev = cabs(slot(J, SC_ALPHA)[j - 1]);
+        const double sprev = (j >= 3) ? sqrt(cabs(cmul(slot(J, SC_BETA)[j - 2], slot(J, SC_GAMMA)[j - 2]))) : 0.0;
+        const double S = aprev + sprev;
+        if (nr <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_VN)[j - 1].x ||
+            nl <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_WN)[j - 1].x) {
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
+            return;
+        }
+        if (cabs(delta) <= SERIOUS_TAU * nr * nl) {
+            if (b0) {
+                J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1;
+                J.status[ST_STATUS] = NKS_E_BREAKDOWN; J.status[ST_BDITER] = j - 1;
+            }
+            return;
+        }
+        const double2 beta = csqrt_principal(delta);
+        const double2 gamma = cdiv(cconj(delta), beta);
+        sv = crecip(beta);
+        sw = crecip(cconj(gamma));
+        cv = cmul(gamma, slot(J, SC_SV)[j - 1]);              // gamma_{j-1} v_{j-1}
+        cw = cmul(cconj(beta), slot(J, SC_SW)[j - 1]);        // conj(beta_{j-1}) w_{j-1}
+        if (b0) {
+            slot(J, SC_BETA)[j - 1] = beta; slot(J, SC_GAMMA)[j - 1] = gamma;
+            slot(J, SC_SV)[j] = sv; slot(J, SC_SW)[j] = sw;
+            slot(J, SC_VN)[j] = mk(nr / cabs(beta), 0.0);
+            slot(J, SC_WN)[j] = mk(nl / cabs(gamma), 0.0);
+        }
+    }
+    const int site = blockIdx.x * NT + threadIdx.x;
+    double2 part = mk(0.0, 0.0);
+    if (site < g.V) {
+        const cx_t<R>* uj = column<R>(J, j, n);
+        const cx_t<R>* tj = lvec<R>(J, j, n);
+        R cf[2][4], cb[2][4];
+        hop_coefs<R>(kappa, mu, cf[0], cb[0]);     // A
+        hop_coefs<R>(kappa, -mu, cf[1], cb[1]);    // A^dagger = A(-mu)
+        const cx_t<R>* const fields[2] = {uj, tj};
+        cx_t<R> acc[2][12];
+        wilson_site<R, 2>(g, links, fields, cf, cb, site, acc);
+        const cx_t<R>* up = (j >= 2) ? column<R>(J, j - 1, n) : nullptr;
+        cx_t<R>* tl = lvec<R>(J, j + 1, n);        // holds t_{j-1}; overwritten by l (own site only)
+        cx_t<R>* rout = (j < J.k) ? column<R>(J, j + 1, n) : nullptr;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const size_t e = (size_t)c * g.V + site;
+            double2 r = cmul(sv, to_d2<R>(acc[0][c]));
+            double2 l = cmul(sw, to_d2<R>(acc[1][c]));
+            if (up) {
+                r = csub(r, cmul(cv, to_d2<R>(up[e])));
+                l = csub(l, cmul(cw, to_d2<R>(tl[e])));
+            }
+            const cx_t<R> rs = from_d2<R>(r);
+            if (rout) { rout[e] = rs; tl[e] = from_d2<R>(l); }
+            part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
+        }
+    }
+    const double2 s = block_sum<NT>(part, lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + blockIdx.x] = s;
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (j >= J.k || J.status[ST_DONE]) return;
+    __shared__ double2 lds[NT / 64];
+    const int n = 12 * V;
+    const double2 sv = slot(J, SC_SV)[j], sw = slot(J, SC_SW)[j];
+    const double2 alpha = cmul(cconj(sw), sum_partials<NT>(J.part + (size_t)PS_S * nblocks, nblocks, lds));
+    if (blockIdx.x == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = alpha;
+    const double2 cu = cmul(alpha, sv);                 // alpha v_j = cu u_j
+    const double2 ct = cmul(cconj(alpha), sw);          // conj(alpha) w_j = ct t_j
+    const int site = blockIdx.x * NT + threadIdx.x;
+    double2 d = mk(0.0, 0.0);
+    double nr2 = 0.0, nl2 = 0.0;
+    if (site < V) {
+        const cx_t<R>* uj = column<R>(J, j, n);
+        const cx_t<R>* tj = lvec<R>(J, j, n);
+        cx_t<R>* r = column<R>(J, j + 1, n);
+        cx_t<R>* l = lvec<R>(J, j + 1, n);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const size_t e = (size_t)c * V + site;
+            const cx_t<R> rv = from_d2<R>(csub(to_d2<R>(r[e]), cmul(cu, to_d2<R>(uj[e]))));
+            const cx_t<R> lv = from_d2<R>(csub(to_d2<R>(l[e]), cmul(ct, to_d2<R>(tj[e]))));
+            r[e] = rv;
+            l[e] = lv;
+            const double2 rd = to_d2<R>(rv), ld = to_d2<R>(lv);
+            d = cadd(d, cmulc(rd, ld));                      // r^dagger l
+            nr2 += cabs2(rd);
+            nl2 += cabs2(ld);
+        }
+    }
+    double2 s = block_sum<NT>(d, lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + blockIdx.x] = s;
+    s = block_sum<NT>(mk(nr2, 0.0), lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_R1 * nblocks + blockIdx.x] = s;
+    s = block_sum<NT>(mk(nl2, 0.0), lds);
+    if (threadIdx.x == 0) J.part[(size_t)PS_R2 * nblocks + blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------------ lift
+constexpr int LIFT_NT = 256;
+
+template <typename R>
+__global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
+    const JobDesc& J = jobs[blockIdx.y];
+    const int n = 12 * V;
+    const int e = blockIdx.x * LIFT_NT + threadIdx.x;   // e = comp * V + site
+    if (e >= n) return;
+    const int c = e / V, s = e - c * V;
+    const int kused = J.status[ST_KUSED];
+    double2 acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
+    const cx_t<R>* base = reinterpret_cast<const cx_t<R>*>(J.vstore) + e;
+    int jj = 0;
+    for (; jj + 1 < kused; jj += 2) {
+        const double2 a = to_d2<R>(base[(size_t)jj * n]);
+        const double2 b = to_d2<R>(base[(size_t)(jj + 1) * n]);
+        acc0 = cadd(acc0, cmul(J.omega[jj], a));
+        acc1 = cadd(acc1, cmul(J.omega[jj + 1], b));
+    }
+    if (jj < kused) acc0 = cadd(acc0, cmul(J.omega[jj], to_d2<R>(base[(size_t)jj * n])));
+    J.x[(size_t)12 * s + c] = cadd(acc0, acc1);
+}
+
+}  // namespace
+
+void launch_pack(const OuterLaunch& L, hipStream_t s) {
+    dim3 grid(L.nblocks, L.njobs);
+    if (L.precision == NKS_FP64)
+        hipLaunchKernelGGL(pack_kernel<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
+    else
+        hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
+}
+
+void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s) {
+    dim3 grid(L.nblocks, L.njobs);
+    if (L.precision == NKS_FP64) {
+        auto links = static_cast<const double2*>(L.links);
+        if (!L.two_sided)
+            hipLaunchKernelGGL(herm_S<double>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks);
+        else
+            hipLaunchKernelGGL(bi_S<double>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j, L.nblocks);
+    } else {
+        auto links = static_cast<const float2*>(L.links);
+        if (!L.two_sided)
+            hipLaunchKernelGGL(herm_S<float>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks);
+        else
+            hipLaunchKernelGGL(bi_S<float>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j, L.nblocks);
+    }
+}
+
+void launch_outer_R(const OuterLaunch& L, int j, hipStream_t s) {
+    dim3 grid(L.nblocks, L.njobs);
+    if (L.precision == NKS_FP64) {
+        if (!L.two_sided) hipLaunchKernelGGL(herm_R<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
+        else hipLaunchKernelGGL(bi_R<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
+    } else {
+        if (!L.two_sided) hipLaunchKernelGGL(herm_R<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
+        else hipLaunchKernelGGL(bi_R<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
+    }
+}
+
+void launch_lift(const OuterLaunch& L, hipStream_t s) {
+    const int n = 12 * L.g.V;
+    dim3 grid((n + LIFT_NT - 1) / LIFT_NT, L.njobs);
+    if (L.precision == NKS_FP64)
+        hipLaunchKernelGGL(lift_kernel<double>, grid, dim3(LIFT_NT), 0, s, L.jobs, L.g.V);
+    else
+        hipLaunchKernelGGL(lift_kernel<float>, grid, dim3(LIFT_NT), 0, s, L.jobs, L.g.V);
+}
+
+}  // namespace nks

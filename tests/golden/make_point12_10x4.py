@@ -1,0 +1,79 @@
+"""Write tests/golden/point12_10x4.json: the oracle's converged sgn(A) b for the
+12 spin-colour point sources at the origin of the 10^4 lattice (eps = 0.35,
+link seed 10401, m0 = 1.6) at mu = 0 and mu = 0.2, sampled at 256 indices per
+source (the 128 largest entries and 128 seeded random ones), plus the full
+norm of each result.
+
+Calls only ``oracle`` and ``nks_inputs``.  The reference is the non-nested
+Krylov-Ritz result (Eqs. non-nested / non-nested-oblique) at k = 1400 with the
+spectral sign of H_k; the change from k = 1200 is recorded as its accuracy.
+Takes ~15 minutes on 4 cores.  Usage: python tests/golden/make_point12_10x4.py
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "4")
+
+import nks_inputs as I  # noqa: E402
+from oracle import dirac, krylov, signfun  # noqa: E402
+
+DIMS = (10, 10, 10, 10)
+K_REF, K_CHECK = 1400, 1200
+NSAMP = 128
+
+
+def sign_e1(alpha, beta, gamma, hermitian):
+    k = len(alpha)
+    h = np.diag(alpha.astype(complex))
+    h += np.diag(beta.astype(complex), -1) + np.diag(gamma.astype(complex), 1)
+    if hermitian:
+        h = h.real
+    return signfun.sign_eig(h, hermitian=hermitian)[:, 0]
+
+
+def main():
+    links = I.su3_links(DIMS, 0.35, 10401)
+    out = {"dims": DIMS, "eps": 0.35, "link_seed": 10401, "m0": 1.6, "k_ref": K_REF,
+           "method": "oracle non-nested Krylov-Ritz, spectral sign of H_k", "cases": []}
+    rng = np.random.default_rng(20261203)
+    rand_idx = np.sort(rng.choice(12 * int(np.prod(DIMS)), NSAMP, replace=False))
+    for mu in (0.0, 0.2):
+        op = dirac.Operator(links, DIMS, 1.6, mu)
+        for spin in range(4):
+            for colour in range(3):
+                t = time.time()
+                b = I.point_source(DIMS, spin, colour).ravel()
+                if mu == 0.0:
+                    kr = krylov.lanczos(op.matvec, b, K_REF)
+                else:
+                    kr = krylov.two_sided_lanczos(op.matvec, op.rmatvec, b, K_REF)
+                c = sign_e1(kr.alpha, kr.beta, kr.gamma, mu == 0.0)
+                y = kr.bnorm * (kr.V @ c)
+                kc = min(K_CHECK, kr.k_used)
+                c2 = sign_e1(kr.alpha[:kc], kr.beta[:kc - 1], kr.gamma[:kc - 1], mu == 0.0)
+                y2 = kr.bnorm * (kr.V[:, :kc] @ c2)
+                change = float(np.linalg.norm(y - y2) / np.linalg.norm(y))
+                big = np.argsort(-np.abs(y))[:NSAMP]
+                idx = np.unique(np.concatenate([big, rand_idx]))
+                out["cases"].append({
+                    "mu": mu, "spin": spin, "colour": colour, "k_used": int(kr.k_used),
+                    "norm": float(np.linalg.norm(y)), "change_k1200": change,
+                    "idx": idx.tolist(),
+                    "re": y[idx].real.tolist(), "im": y[idx].imag.tolist(),
+                })
+                print(f"mu={mu} spin={spin} colour={colour}: |y|={np.linalg.norm(y):.6f} "
+                      f"change(k={kc}->{kr.k_used})={change:.2e} ({time.time() - t:.0f} s)", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "point12_10x4.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

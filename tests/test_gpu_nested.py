@@ -1,0 +1,91 @@
+"""GPU parity of the nested step (App. C steps 3-5: p, LU of pH_k, inner
+Krylov space of H_k', Roberts-Higham on H_ell) on the very same tridiagonal
+H_k that the oracle's Lanczos produced, at the C1 (4^4, k=200, ell=50) and
+C2 (8^4, mu=0.3, k=800, ell=150) sizes."""
+import functools
+
+import numpy as np
+import pytest
+
+import nks_inputs as I
+from gpu_common import ctx, operator, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def ritz(dims, eps, seed, mu, k, src_seed):
+    from oracle import krylov
+    op = operator(dims, eps, seed, mu)
+    b = I.gaussian_source(dims, src_seed).ravel()
+    if mu == 0.0:
+        return krylov.lanczos(op.matvec, b, k)
+    return krylov.two_sided_lanczos(op.matvec, op.rmatvec, b, k)
+
+
+CASES = [
+    ((4, 4, 4, 4), 0.5, 4401, 0.0, 200, 4402, 50),
+    ((4, 4, 4, 4), 0.5, 4401, 0.3, 200, 4402, 50),
+    ((8, 8, 8, 8), 0.4, 8401, 0.3, 800, 8402, 150),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=["c1-herm", "4x4-mu0.3", "c2-8x4-mu0.3"])
+def test_nested_step_matches_oracle_at_given_p(case):
+    import paper_0912_4457_amd as nks
+    from oracle import nested
+    dims, eps, seed, mu, k, src, ell = case
+    kr = ritz(dims, eps, seed, mu, k, src)
+    herm = mu == 0.0
+    c_ref, info = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, herm, ell)
+    c_gpu, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, ell, p=info["p"])
+    assert st["status"] == 0
+    assert st["ell_used"] == info["ell"]
+    assert rel(c_gpu, c_ref) <= (1e-11 if herm else 1e-9)
+
+
+@pytest.mark.parametrize("case", CASES, ids=["c1-herm", "4x4-mu0.3", "c2-8x4-mu0.3"])
+def test_nested_step_auto_p(case):
+    import paper_0912_4457_amd as nks
+    from oracle import nested
+    dims, eps, seed, mu, k, src, ell = case
+    kr = ritz(dims, eps, seed, mu, k, src)
+    herm = mu == 0.0
+    zmin, zmax = nested.ritz_extremes(kr.alpha, kr.beta, kr.gamma, herm)
+    c_gpu, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, ell)
+    if herm:   # Sturm multisection: exact Ritz extremes
+        assert st["z_min"] == pytest.approx(zmin, rel=1e-5)
+        assert st["z_max"] == pytest.approx(zmax, rel=1e-5)
+    else:      # power / inverse iteration: the two digits p needs
+        assert st["z_max"] == pytest.approx(zmax, rel=0.05)
+        assert st["z_min"] == pytest.approx(zmin, rel=0.5)
+    # the nested result depends on p only through the inner approximation error:
+    # both sides stay as close to the non-nested sgn(H_k) e_1 as the oracle at its p_opt
+    c_nn, _ = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, herm, k)
+    c_or, _ = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, herm, ell)
+    assert rel(c_gpu, c_nn) <= max(10 * rel(c_or, c_nn), 1e-9)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_non_nested_mode_matches_oracle_rhi(mu):
+    import paper_0912_4457_amd as nks
+    from oracle import nested
+    kr = ritz((4, 4, 4, 4), 0.5, 4401, mu, 200, 4402)
+    herm = mu == 0.0
+    c_ref, info = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, herm, 200)
+    assert not info["nested"]
+    c_gpu, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, 200)
+    assert st["ell_used"] == 0 and 6 <= st["rhi_iters"] <= 12
+    assert rel(c_gpu, c_ref) <= 1e-11
+
+
+def test_nested_step_tiny_and_odd_sizes():
+    import paper_0912_4457_amd as nks
+    from oracle import nested
+    rng = np.random.default_rng(3)
+    for k in (1, 2, 3, 7):
+        a = rng.standard_normal(k) * 2
+        b = rng.uniform(0.3, 1.0, max(k - 1, 0))
+        c_ref, _ = nested.nested_coefficients(a, b, b, True, 64)
+        c_gpu, _ = nks.nested_step(ctx(), a, b, b, True, 64)
+        assert rel(c_gpu, c_ref) <= 1e-12
