@@ -81,8 +81,9 @@ enum nks_policy {
 /* Options of one sign application.  Initialise with nks_opts_default(). */
 typedef struct nks_opts {
     size_t size;          /* sizeof(nks_opts), for versioning */
-    int k;                /* outer Krylov size (max k under a policy); rounded up to even */
-    int ell;              /* inner Krylov size; rounded up to even; ell >= k -> non-nested RHi on H_k */
+    int k;                /* outer Krylov size (the largest k under the k policy); rounded up to even */
+    int ell;              /* inner Krylov size (the largest under the ell policy); rounded up to
+                             even; ell >= k -> non-nested RHi on H_k */
     double tol;           /* target relative accuracy for the policies */
     int precision;        /* enum nks_precision */
     double p;             /* preconditioner factor of Eq. precond; <= 0 -> p_opt of Eq. popt
@@ -180,6 +181,17 @@ int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opt
 int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double* beta_host,
                     const double* gamma_host, int hermitian, const nks_opts* opts,
                     double* c_host, nks_stats* stats);
+
+/* Launch-shape choices of the outer passes, per context (an autotuner sets
+ * them after timing the alternatives):
+ *   "xcd_map"    1: 1D grid that keeps every job of a site block on one XCD
+ *                0: 2D grid (site block, job)
+ *   "split_dual" 1: the two-sided stencil computes A u and A^dagger t in
+ *                separate workgroups; 0: one thread does both.
+ * Results are identical bit for bit under every choice.  Unknown keys give
+ * NKS_E_INVALID. */
+int nks_tune_set(nks_ctx* ctx, const char* key, int value);
+int nks_tune_get(nks_ctx* ctx, const char* key, int* value);
 
 /* Measurement support.  When enabled on a context, sign applications bracket
  * every 8th launch of each kernel class with HIP events on the call's stream

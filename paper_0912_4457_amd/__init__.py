@@ -88,6 +88,8 @@ SIGNATURES = {
     "nks_outer_basis": (_I, [_VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, _PD, _PD, _PD,
                              ctypes.POINTER(Stats)]),
     "nks_nested_step": (_I, [_VP, _I, _PD, _PD, _PD, _I, ctypes.POINTER(Opts), _PD, ctypes.POINTER(Stats)]),
+    "nks_tune_set": (_I, [_VP, ctypes.c_char_p, _I]),
+    "nks_tune_get": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
     "nks_profile_enable": (_I, [_VP, _I]),
     "nks_profile_read": (_I, [_VP, _I, ctypes.POINTER(ctypes.c_int), _PD, _PD]),
 }
@@ -159,6 +161,14 @@ class Context:
             self._ws = None
             self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
+
+    def tune_set(self, key: str, value: int):
+        self.check(lib().nks_tune_set(self.h, key.encode(), int(value)))
+
+    def tune_get(self, key: str) -> int:
+        v = ctypes.c_int()
+        self.check(lib().nks_tune_get(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
 
     def profile(self, enable: bool = True):
         """Sample kernel durations with HIP events (see nks_profile_enable)."""
@@ -300,7 +310,8 @@ def sign_apply_batch(jobs, stats: bool = True):
         x = j.get("x")
         x = torch.empty_like(b) if x is None else x
         o = make_opts(k=j.get("k", 200), ell=j.get("ell", 50), tol=j.get("tol", 1e-8),
-                      precision=j.get("precision", "fp64"), p=j.get("p"))
+                      precision=j.get("precision", "fp64"), p=j.get("p"),
+                      k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED))
         spec.append((lat, b, x, o))
         xs.append(x)
     ctx = spec[0][0].ctx
@@ -341,13 +352,16 @@ def outer_basis(lat: Lattice, b, k: int, precision="fp64"):
 
 
 def nested_step(ctx: Context, alpha, beta, gamma, hermitian: bool, ell: int, p: float | None = None,
-                max_rhi_iter: int = 50, rhi_tol: float = 1e-14):
-    """Steps 3-5 on a given tridiagonal H_k: returns (c ~ sgn(H_k) e_1, stats)."""
+                max_rhi_iter: int = 50, rhi_tol: float = 1e-14, ell_policy: int = POLICY_FIXED,
+                tol: float = 1e-8):
+    """Steps 3-5 on a given tridiagonal H_k: returns (c ~ sgn(H_k) e_1, stats).
+
+    With ell_policy=POLICY_DOUBLING, ``ell`` is the largest inner size allowed."""
     alpha = np.ascontiguousarray(alpha, dtype=np.complex128)
     k = alpha.size
     beta = np.ascontiguousarray(beta if k > 1 else np.zeros(1), dtype=np.complex128)
     gamma = np.ascontiguousarray(gamma if k > 1 else np.zeros(1), dtype=np.complex128)
-    o = make_opts(k=k, ell=ell, p=p, max_rhi_iter=max_rhi_iter, rhi_tol=rhi_tol)
+    o = make_opts(k=k, ell=ell, p=p, max_rhi_iter=max_rhi_iter, rhi_tol=rhi_tol, ell_policy=ell_policy, tol=tol)
     c = np.zeros(k, dtype=np.complex128)
     st = Stats()
     P = lambda arr_: arr_.view(np.float64).ctypes.data_as(_PD)  # noqa: E731

@@ -1,6 +1,7 @@
 // C ABI of libnks: contexts, lattices, workspace planning and the launch
 // sequence of a (batched) sign application.
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -29,6 +30,7 @@ struct nks_ctx {
     std::vector<hipEvent_t> pool;
     std::vector<ProfRecord> pending;
     long long prof_count[NKS_K_COUNT] = {0, 0, 0, 0};
+    Tuning tune;
 };
 
 struct nks_lattice {
@@ -78,7 +80,9 @@ struct JobPlan {
     int max_rhi;
     double rhi_tol;
     int nblocks, lcap;
-    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_nest, end;
+    int k_policy, ell_policy;
+    double tol;
+    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_nest, end;
 };
 
 struct Plan {
@@ -97,8 +101,11 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
         return fail(ctx, NKS_E_INVALID, "unknown precision");
     if (o->max_rhi_iter < 1) return fail(ctx, NKS_E_INVALID, "max_rhi_iter must be >= 1");
     if (!(o->rhi_tol > 0.0)) return fail(ctx, NKS_E_INVALID, "rhi_tol must be > 0");
-    if (o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED)
-        return fail(ctx, NKS_E_UNSUPPORTED, "policy not available in this entry point");
+    if (o->k_policy < NKS_POLICY_FIXED || o->k_policy > NKS_POLICY_DOUBLING ||
+        o->ell_policy < NKS_POLICY_FIXED || o->ell_policy > NKS_POLICY_DOUBLING)
+        return fail(ctx, NKS_E_UNSUPPORTED, "policy not available");
+    if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
+        return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
     return NKS_OK;
 }
 
@@ -120,6 +127,9 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
         jp.p = J.opts->p;
         jp.max_rhi = J.opts->max_rhi_iter;
         jp.rhi_tol = J.opts->rhi_tol;
+        jp.k_policy = J.opts->k_policy;
+        jp.ell_policy = J.opts->ell_policy;
+        jp.tol = J.opts->tol;
         jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
         if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
             return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
@@ -151,6 +161,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
         jp.off_status = off; off = align_up(off + sizeof(int) * ST_COUNT);
         jp.off_report = off; off = align_up(off + sizeof(double) * RP_COUNT);
         jp.off_omega = off; off = align_up(off + sizeof(double2) * jp.k);
+        jp.off_ckpt = off; off = align_up(off + (jp.k_policy != NKS_POLICY_FIXED ? sizeof(double2) * jp.k : 0));
         jp.off_nest = off; off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided));
         jp.end = off;
     }
@@ -181,10 +192,14 @@ JobDesc make_desc(const JobPlan& jp, char* ws, const void* b, void* x) {
     d.scstride = jp.k + 2;
     d.nblocks = jp.nblocks;
     d.precision = jp.precision;
+    d.k_policy = jp.k_policy;
+    d.ell_policy = jp.ell_policy;
+    d.tol = jp.tol;
+    d.ckpt = jp.k_policy != NKS_POLICY_FIXED ? reinterpret_cast<double2*>(ws + jp.off_ckpt) : nullptr;
     return d;
 }
 
-OuterLaunch group_launch(const Plan& P, int gi, JobDesc* table) {
+OuterLaunch group_launch(const nks_ctx* ctx, const Plan& P, int gi, JobDesc* table) {
     const auto [start, count] = P.groups[gi];
     const JobPlan& jp = P.jobs[start];
     OuterLaunch L{};
@@ -199,6 +214,7 @@ OuterLaunch group_launch(const Plan& P, int gi, JobDesc* table) {
     L.nblocks = jp.nblocks;
     L.precision = jp.precision;
     L.two_sided = jp.two_sided;
+    L.tune = ctx->tune;
     return L;
 }
 
@@ -259,8 +275,10 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
     HIP_TRY(ctx, hipMemcpyAsync(table, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
-        OuterLaunch L = group_launch(P, (int)gi, table);
+        OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const int start = P.groups[gi].first;
+        bool kpol = false;
+        for (int i = start; i < start + L.njobs; ++i) kpol = kpol || P.jobs[i].k_policy != NKS_POLICY_FIXED;
         launch_pack(L, s);
         for (int j = 1; j <= L.kmax; ++j) {
             int r = prof_begin(ctx, NKS_K_STENCIL, ctx->prof ? bytes_S(L, P, start, j) : 0.0, s);
@@ -270,6 +288,7 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
                 r = prof_begin(ctx, NKS_K_RECUR, ctx->prof ? bytes_R(L, P, start, j) : 0.0, s);
                 launch_outer_R(L, j, s);
                 prof_end(ctx, r, s);
+                if (kpol && j % CKPT_DK == 0) launch_checkpoint(L.jobs, L.njobs, j, s);
             }
         }
     }
@@ -288,7 +307,7 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
-        OuterLaunch L = group_launch(P, (int)gi, table);
+        OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const long long c = ctx->prof_count[NKS_K_LIFT];
         ctx->prof_count[NKS_K_LIFT] = 0;
         int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, s);
@@ -361,6 +380,8 @@ int nks_create(int device, nks_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return NKS_E_HIP;
     auto* c = new nks_ctx();
     c->device = device;
+    if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = atoi(e) != 0;
+    if (const char* e = getenv("NKS_SPLIT_DUAL")) c->tune.split_dual = atoi(e) != 0;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return NKS_E_HIP; }
     *out = c;
@@ -597,6 +618,9 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
     d.lcap = lcap;
     d.scstride = (int)stride;
     d.precision = NKS_FP64;
+    d.k_policy = NKS_POLICY_FIXED;
+    d.ell_policy = opts->ell_policy;
+    d.tol = opts->tol;
     HIP_TRY(ctx, hipMemcpy(w, &d, sizeof(d), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(w + off_sc, sc.data(), sizeof(double2) * sc.size(), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(w + off_st, st, sizeof(st), hipMemcpyHostToDevice));
@@ -617,7 +641,26 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
         stats->z_min = rp[RP_ZMIN];
         stats->z_max = rp[RP_ZMAX];
         stats->b_norm = 1.0;
+        stats->inner_delta = rp[RP_INNER_DELTA];
     }
+    return NKS_OK;
+}
+
+int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
+    if (!ctx || !key) return NKS_E_INVALID;
+    const std::string k(key);
+    if (k == "xcd_map") ctx->tune.xcd_map = value != 0;
+    else if (k == "split_dual") ctx->tune.split_dual = value != 0;
+    else return fail(ctx, NKS_E_INVALID, "unknown tuning key " + k);
+    return NKS_OK;
+}
+
+int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
+    if (!ctx || !key || !value) return NKS_E_INVALID;
+    const std::string k(key);
+    if (k == "xcd_map") *value = ctx->tune.xcd_map;
+    else if (k == "split_dual") *value = ctx->tune.split_dual;
+    else return fail(ctx, NKS_E_INVALID, "unknown tuning key " + k);
     return NKS_OK;
 }
 

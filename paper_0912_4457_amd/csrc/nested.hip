@@ -25,6 +25,7 @@ constexpr double RHI_NEAR = 1e-8;          // one more step once the change is b
 constexpr double LUCKY_TAU_HERMITIAN = 1e-10;
 constexpr double LUCKY_TAU_TWO_SIDED = 1e-8;
 constexpr double SERIOUS_TAU = 1e-12;
+constexpr int ELL0 = 16;                   // first inner size of ell-doubling
 
 // ---- scalar helpers for T = double (real) or double2 (complex)
 __device__ inline double s_mul(double a, double b) { return a * b; }
@@ -313,6 +314,7 @@ struct NestPtrs {
     int* piv;                   // k
     void* vl;                   // inner basis, L columns of k
     void *v, *vp, *w, *wp, *r, *l, *y, *t;   // work vectors (k)
+    void *cc, *cp;              // current and previous coefficient vectors (k)
     void *al, *bl, *gl;         // H_ell (L)
     void *S, *B;                // dense L x L
     void *prow, *fcol;          // L
@@ -321,7 +323,7 @@ struct NestPtrs {
 
 __host__ __device__ inline size_t nest_words_impl(int k, int L) {
     // complex words (16 bytes); int arrays rounded up
-    return (size_t)3 * k + 4 * (size_t)k + ((size_t)k + 3) / 4 + (size_t)k * L + 8 * (size_t)k + 3 * (size_t)L +
+    return (size_t)3 * k + 4 * (size_t)k + ((size_t)k + 3) / 4 + (size_t)k * L + 10 * (size_t)k + 3 * (size_t)L +
            2 * (size_t)L * L + 2 * (size_t)L + ((size_t)L + 3) / 4 + 8;
 }
 
@@ -334,7 +336,7 @@ __device__ inline NestPtrs nest_ptrs(double2* base, int k, int L) {
     P.piv = (int*)take(((size_t)k + 3) / 4);
     P.vl = take((size_t)k * L);
     P.v = take(k); P.vp = take(k); P.w = take(k); P.wp = take(k); P.r = take(k); P.l = take(k); P.y = take(k);
-    P.t = take(k);
+    P.t = take(k); P.cc = take(k); P.cp = take(k);
     P.al = take(L); P.bl = take(L); P.gl = take(L);
     P.S = take((size_t)L * L); P.B = take((size_t)L * L);
     P.prow = take(L); P.fcol = take(L);
@@ -474,230 +476,204 @@ __device__ int rhi(T* S, T* B, int n, int maxit, double tol, T* prow, T* fcol, i
     return -maxit;
 }
 
+struct Smem {
+    double2* red;     // NT/64
+    double* redd;     // NT/64
+    int* redi;        // NT/64
+    void* scan;       // NT affine maps
+};
+
+// ---------------------------------------------------------------- step 3: p
+// Estimated Ritz-value extremes of the tridiagonal H_k (in P.d/sub/sup).
 template <typename T>
-__device__ void nested_job(const JobDesc& J, double2* lds, double* ldsd, int* ldsi, void* scan_lds) {
+__device__ void estimate_extremes(const JobDesc& J, const NestPtrs& P, int k, const Smem& sm, double& zmin,
+                                  double& zmax) {
     constexpr bool CPLX = sizeof(T) == sizeof(double2);
     const int tid = threadIdx.x;
-    double2* sc = J.sc;
-    const size_t st = J.scstride;
-    double2* ALPHA = sc + SC_ALPHA * st;
-    double2* BETA = sc + SC_BETA * st;
-    double2* GAMMA = sc + SC_GAMMA * st;
-    double2* SV = sc + SC_SV * st;
-    double2* SW = sc + SC_SW * st;
-    const int kused = J.status[ST_KUSED];
-    if (kused == 0) return;                              // zero source; lift writes zeros
-    const int k = kused;
-    const double bnorm = J.report[RP_BNORM];
-    int ell = J.ell;
-    const bool nonnested = ell >= k;
-    const int L = nonnested ? k : ell;
-    NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
-    T* d = (T*)P.d;
-    T* sub = (T*)P.sub;
-    T* sup = (T*)P.sup;
+    const T* d = (const T*)P.d;
+    const T* sub = (const T*)P.sub;
+    const T* sup = (const T*)P.sup;
+    if (!CPLX) {
+        // Ritz values of the real symmetric H_k by Sturm multisection
+        const double2* dd = (const double2*)(J.sc + (size_t)SC_ALPHA * J.scstride + 1);
+        const double2* ee = (const double2*)(J.sc + (size_t)SC_BETA * J.scstride + 1);
+        double g = 0.0, emax = 0.0;
+        for (int i = tid; i < k; i += NT) {
+            const double el = (i > 0) ? fabs(ee[i - 1].x) : 0.0;
+            const double er = (i + 1 < k) ? fabs(ee[i].x) : 0.0;
+            g = fmax(g, fabs(dd[i].x) + el + er);
+            emax = fmax(emax, er);
+        }
+        const double G = block_max(g, sm.redd) * 1.001 + 1e-300;
+        const double em = block_max(emax, sm.redd);
+        const double pivmin = 2.2250738585072014e-308 * fmax(1.0, em * em);
+        __shared__ int c0s;
+        if (tid == 0) c0s = sturm_count(dd, ee, k, 0.0, pivmin);
+        __syncthreads();
+        const int c0 = c0s;
+        __syncthreads();
+        const double l1 = find_eig(dd, ee, k, 1, G, pivmin, sm.redd);
+        const double lk = find_eig(dd, ee, k, k, G, pivmin, sm.redd);
+        zmax = fmax(fabs(l1), fabs(lk));
+        if (c0 == 0) zmin = fabs(l1);
+        else if (c0 == k) zmin = fabs(lk);
+        else {
+            const double ln = find_eig(dd, ee, k, c0, G, pivmin, sm.redd);
+            const double lp = find_eig(dd, ee, k, c0 + 1, G, pivmin, sm.redd);
+            zmin = fmin(fabs(ln), fabs(lp));
+        }
+        return;
+    }
+    // power iteration for z_max, inverse iteration (LU of H_k) for z_min; each
+    // estimate is the geometric mean of the per-step growth over the second
+    // half of the iterations, which damps the transient growth of a non-normal H_k
+    constexpr int NIT = 48, NAVG = 24;
+    T* x = (T*)P.v;
+    T* y = (T*)P.w;
+    T* lf = (T*)P.lf;
+    T* u0 = (T*)P.u0;
+    T* u1 = (T*)P.u1;
+    T* u2 = (T*)P.u2;
+    for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+    __syncthreads();
+    double nx = sqrt(block_norm2<T>(x, k, sm.red));
+    for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
+    __syncthreads();
+    double lsum = 0.0;
+    for (int it = 0; it < NIT; ++it) {
+        for (int i = tid; i < k; i += NT) {
+            T hv = s_mul(d[i], x[i]);
+            if (i > 0) hv = s_add(hv, s_mul(sub[i - 1], x[i - 1]));
+            if (i + 1 < k) hv = s_add(hv, s_mul(sup[i], x[i + 1]));
+            y[i] = hv;
+        }
+        __syncthreads();
+        const double ny = sqrt(block_norm2<T>(y, k, sm.red));
+        if (it >= NIT - NAVG) lsum += log(ny);
+        for (int i = tid; i < k; i += NT) x[i] = s_scale(y[i], 1.0 / ny);
+        __syncthreads();
+    }
+    zmax = exp(lsum / NAVG);
     for (int i = tid; i < k; i += NT) {
-        d[i] = s_from<T>(ALPHA[i + 1]);
-        if (i + 1 < k) { sub[i] = s_from<T>(BETA[i + 1]); sup[i] = s_from<T>(GAMMA[i + 1]); }
+        u0[i] = d[i];
+        if (i + 1 < k) { lf[i] = sub[i]; u1[i] = sup[i]; }
     }
     __syncthreads();
-    T* S = (T*)P.S;
-    T* B = (T*)P.B;
-    T* s_e1 = (T*)P.y;   // first column of sgn(H_ell)
-    int ell_used = 0, rhi_it = 0;
-    double p_used = 0.0, zmin = 0.0, zmax = 0.0;
-    T* vl = (T*)P.vl;
-    if (nonnested) {
-        for (int e = tid; e < k * k; e += NT) {
-            const int i = e / k, j = e - i * k;
-            T v = s_zero<T>();
-            if (i == j) v = d[i];
-            else if (i == j + 1) v = sub[j];
-            else if (j == i + 1) v = sup[i];
-            S[e] = v;
-        }
-        __syncthreads();
-        rhi_it = rhi<T>(S, B, k, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, lds, ldsd, ldsi);
-        __syncthreads();
-        for (int i = tid; i < k; i += NT) vl[i] = S[(size_t)i * k];   // c = S e_1
-        ell_used = 0;
-        __syncthreads();
-    } else {
-        // ---------------------------------------------------- step 3: p and LU
-        double p = J.p;
-        T* lf = (T*)P.lf;
-        T* u0 = (T*)P.u0;
-        T* u1 = (T*)P.u1;
-        T* u2 = (T*)P.u2;
-        if (p <= 0.0) {
-            if (!CPLX) {
-                // Ritz values of the real symmetric H_k by Sturm multisection
-                double g = 0.0;
-                const double2* dd = reinterpret_cast<const double2*>(ALPHA + 1);
-                const double2* ee = reinterpret_cast<const double2*>(BETA + 1);
-                double emax = 0.0;
-                for (int i = tid; i < k; i += NT) {
-                    const double el = (i > 0) ? fabs(ee[i - 1].x) : 0.0;
-                    const double er = (i + 1 < k) ? fabs(ee[i].x) : 0.0;
-                    g = fmax(g, fabs(dd[i].x) + el + er);
-                    emax = fmax(emax, er);
-                }
-                const double G = block_max(g, ldsd) * 1.001 + 1e-300;
-                const double em = block_max(emax, ldsd);
-                const double pivmin = 2.2250738585072014e-308 * fmax(1.0, em * em);
-                int c0;
-                {
-                    __shared__ int c0s;
-                    if (tid == 0) c0s = sturm_count(dd, ee, k, 0.0, pivmin);
-                    __syncthreads();
-                    c0 = c0s;
-                    __syncthreads();
-                }
-                const double l1 = find_eig(dd, ee, k, 1, G, pivmin, ldsd);
-                const double lk = find_eig(dd, ee, k, k, G, pivmin, ldsd);
-                zmax = fmax(fabs(l1), fabs(lk));
-                if (c0 == 0) zmin = fabs(l1);
-                else if (c0 == k) zmin = fabs(lk);
-                else {
-                    const double ln = find_eig(dd, ee, k, c0, G, pivmin, ldsd);
-                    const double lp = find_eig(dd, ee, k, c0 + 1, G, pivmin, ldsd);
-                    zmin = fmin(fabs(ln), fabs(lp));
-                }
-            } else {
-                // power iteration for z_max, inverse iteration (LU of H_k) for z_min;
-                // each estimate is the geometric mean of the per-step growth over
-                // the second half of the iterations, which damps the transient
-                // growth of a non-normal H_k
-                constexpr int NIT = 48, NAVG = 24;
-                T* x = (T*)P.v;
-                T* y = (T*)P.w;
-                for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
-                __syncthreads();
-                double nx = sqrt(block_norm2<T>(x, k, lds));
-                for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
-                __syncthreads();
-                double lsum = 0.0;
-                for (int it = 0; it < NIT; ++it) {
-                    for (int i = tid; i < k; i += NT) {
-                        T hv = s_mul(d[i], x[i]);
-                        if (i > 0) hv = s_add(hv, s_mul(sub[i - 1], x[i - 1]));
-                        if (i + 1 < k) hv = s_add(hv, s_mul(sup[i], x[i + 1]));
-                        y[i] = hv;
-                    }
-                    __syncthreads();
-                    const double ny = sqrt(block_norm2<T>(y, k, lds));
-                    if (it >= NIT - NAVG) lsum += log(ny);
-                    for (int i = tid; i < k; i += NT) x[i] = s_scale(y[i], 1.0 / ny);
-                    __syncthreads();
-                }
-                zmax = exp(lsum / NAVG);
-                for (int i = tid; i < k; i += NT) {
-                    u0[i] = d[i];
-                    if (i + 1 < k) { lf[i] = sub[i]; u1[i] = sup[i]; }
-                }
-                __syncthreads();
-                __shared__ int info0;
-                if (tid == 0) info0 = gttrf<T>(k, lf, u0, u1, u2, P.piv);
-                __syncthreads();
-                for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
-                __syncthreads();
-                if (info0 == 0) {
-                    const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
-                    lsum = 0.0;
-                    nx = sqrt(block_norm2<T>(x, k, lds));
-                    for (int it = 0; it < NIT; ++it) {
-                        for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
-                        __syncthreads();
-                        solve_n<T>(F, k, x, (T*)P.t, y, scan_lds);
-                        nx = sqrt(block_norm2<T>(y, k, lds));
-                        if (it >= NIT - NAVG) lsum += log(nx);
-                        T* sw_ = x; x = y; y = sw_;
-                    }
-                    zmin = exp(-lsum / NAVG);
-                } else {
-                    zmin = zmax * 1e-3;
-                }
-                __syncthreads();
-            }
-            p = 1.0 / sqrt(zmin * zmax);
-        }
-        p_used = p;
-        for (int i = tid; i < k; i += NT) {
-            u0[i] = s_scale(d[i], p);
-            if (i + 1 < k) { lf[i] = s_scale(sub[i], p); u1[i] = s_scale(sup[i], p); }
-        }
-        __syncthreads();
-        __shared__ int info;
-        if (tid == 0) info = gttrf<T>(k, lf, u0, u1, u2, P.piv);
-        __syncthreads();
-        if (info != 0) {
-            if (tid == 0) J.status[ST_STATUS] = NKS_E_NOCONV;
-            for (int i = tid; i < k; i += NT) J.omega[i] = mk(0.0, 0.0);
-            return;
-        }
-        // ---------------------------------------------------- step 4: inner Krylov space
-        T* v = (T*)P.v;
-        T* vp = (T*)P.vp;
-        T* w = (T*)P.w;
-        T* wp = (T*)P.wp;
-        T* r = (T*)P.r;
-        T* l = (T*)P.l;
-        T* al = (T*)P.al;
-        T* bl = (T*)P.bl;
-        T* gl = (T*)P.gl;
-        for (int i = tid; i < k; i += NT) {
-            v[i] = (i == 0) ? s_one<T>() : s_zero<T>();
-            vp[i] = s_zero<T>();
-            if (CPLX) { w[i] = v[i]; wp[i] = s_zero<T>(); }
-        }
-        __syncthreads();
-        apply_hprime<T, false>(P, k, p, v, r, scan_lds);
-        if (CPLX) apply_hprime<T, true>(P, k, p, w, l, scan_lds);
-        double vn = 1.0, wn = 1.0;
-        ell_used = L;
-        for (int i = 1; i <= L; ++i) {
-            for (int q = tid; q < k; q += NT) vl[(size_t)(i - 1) * k + q] = v[q];
+    __shared__ int info0;
+    if (tid == 0) info0 = gttrf<T>(k, lf, u0, u1, u2, P.piv);
+    __syncthreads();
+    for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+    __syncthreads();
+    if (info0 == 0) {
+        const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
+        lsum = 0.0;
+        nx = sqrt(block_norm2<T>(x, k, sm.red));
+        for (int it = 0; it < NIT; ++it) {
+            for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
             __syncthreads();
+            solve_n<T>(F, k, x, (T*)P.t, y, sm.scan);
+            nx = sqrt(block_norm2<T>(y, k, sm.red));
+            if (it >= NIT - NAVG) lsum += log(nx);
+            T* sw_ = x; x = y; y = sw_;
+        }
+        zmin = exp(-lsum / NAVG);
+    } else {
+        zmin = zmax * 1e-3;
+    }
+    __syncthreads();
+}
+
+// LU of p H_k into the nest area; returns the ?gttrf info (0 = nonsingular)
+template <typename T>
+__device__ int lu_pH(const NestPtrs& P, int k, double p) {
+    const T* d = (const T*)P.d;
+    const T* sub = (const T*)P.sub;
+    const T* sup = (const T*)P.sup;
+    for (int i = threadIdx.x; i < k; i += NT) {
+        ((T*)P.u0)[i] = s_scale(d[i], p);
+        if (i + 1 < k) { ((T*)P.lf)[i] = s_scale(sub[i], p); ((T*)P.u1)[i] = s_scale(sup[i], p); }
+    }
+    __syncthreads();
+    __shared__ int info;
+    if (threadIdx.x == 0) info = gttrf<T>(k, (T*)P.lf, (T*)P.u0, (T*)P.u1, (T*)P.u2, P.piv);
+    __syncthreads();
+    const int r = info;
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------- step 4: inner Krylov space
+// The inner (two-sided) Lanczos process on H_k' from e_1, resumable so that
+// ell-doubling extends the same space instead of restarting it.
+struct Inner {
+    int i = 0;          // basis vectors built so far (H_i is i x i)
+    bool ended = false; // lucky or serious breakdown: the space cannot grow
+    bool serious = false;
+    double vn = 1.0, wn = 1.0;
+};
+
+template <typename T>
+__device__ void inner_init(const NestPtrs& P, int k, double p, Inner& st, const Smem& sm) {
+    constexpr bool CPLX = sizeof(T) == sizeof(double2);
+    T* v = (T*)P.v;
+    T* vp = (T*)P.vp;
+    T* w = (T*)P.w;
+    T* wp = (T*)P.wp;
+    for (int i = threadIdx.x; i < k; i += NT) {
+        v[i] = (i == 0) ? s_one<T>() : s_zero<T>();
+        vp[i] = s_zero<T>();
+        if (CPLX) { w[i] = v[i]; wp[i] = s_zero<T>(); }
+    }
+    __syncthreads();
+    apply_hprime<T, false>(P, k, p, v, (T*)P.r, sm.scan);
+    if (CPLX) apply_hprime<T, true>(P, k, p, w, (T*)P.l, sm.scan);
+    st = Inner{};
+}
+
+// Grow the inner space to m vectors (or until it breaks down).
+template <typename T>
+__device__ void inner_extend(const NestPtrs& P, int k, double p, int m, Inner& st, const Smem& sm) {
+    constexpr bool CPLX = sizeof(T) == sizeof(double2);
+    const int tid = threadIdx.x;
+    T* v = (T*)P.v;
+    T* vp = (T*)P.vp;
+    T* w = (T*)P.w;
+    T* wp = (T*)P.wp;
+    T* r = (T*)P.r;
+    T* l = (T*)P.l;
+    T* al = (T*)P.al;
+    T* bl = (T*)P.bl;
+    T* gl = (T*)P.gl;
+    T* vl = (T*)P.vl;
+    while (st.i < m && !st.ended) {
+        const int i = st.i;   // vectors so far; next vector is number i+1
+        if (i > 0) {
+            // finish step i: beta_i, gamma_i and v_{i+1}
             if (!CPLX) {
-                const double a = s_d2(block_dot<T>(v, r, k, lds)).x;
-                if (tid == 0) al[i - 1] = s_from<T>(mk(a, 0.0));
-                for (int q = tid; q < k; q += NT) r[q] = s_sub(r[q], s_scale(v[q], a));
-                __syncthreads();
-                if (i == L) break;
-                const double b = sqrt(block_norm2<T>(r, k, lds));
+                const double a = s_d2(al[i - 1]).x;
+                const double b = sqrt(block_norm2<T>(r, k, sm.red));
                 const double bprev = (i >= 2) ? s_d2(bl[i - 2]).x : 0.0;
-                if (b <= LUCKY_TAU_HERMITIAN * (fabs(a) + bprev)) { ell_used = i; break; }
+                if (b <= LUCKY_TAU_HERMITIAN * (fabs(a) + bprev)) { st.ended = true; break; }
                 if (tid == 0) { bl[i - 1] = s_from<T>(mk(b, 0.0)); gl[i - 1] = bl[i - 1]; }
                 for (int q = tid; q < k; q += NT) {
                     vp[q] = v[q];
                     v[q] = s_scale(r[q], 1.0 / b);
                 }
                 __syncthreads();
-                apply_hprime<T, false>(P, k, p, v, r, scan_lds);
+                apply_hprime<T, false>(P, k, p, v, r, sm.scan);
                 for (int q = tid; q < k; q += NT) r[q] = s_sub(r[q], s_scale(vp[q], b));
                 __syncthreads();
             } else {
-                const double2 a = s_d2(block_dot<T>(w, r, k, lds));
-                if (tid == 0) al[i - 1] = s_from<T>(a);
-                for (int q = tid; q < k; q += NT) {
-                    r[q] = s_sub(r[q], s_mul(s_from<T>(a), v[q]));
-                    l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(a)), w[q]));
-                }
-                __syncthreads();
-                if (i == L) break;
-                const double2 delta = s_d2(block_dot<T>(r, l, k, lds));
-                const double nr = sqrt(block_norm2<T>(r, k, lds));
-                const double nl = sqrt(block_norm2<T>(l, k, lds));
+                const double2 a = s_d2(al[i - 1]);
+                const double2 delta = s_d2(block_dot<T>(r, l, k, sm.red));
+                const double nr = sqrt(block_norm2<T>(r, k, sm.red));
+                const double nl = sqrt(block_norm2<T>(l, k, sm.red));
                 const double S_ = cabs(a) + ((i >= 2) ? sqrt(cabs(cmul(s_d2(bl[i - 2]), s_d2(gl[i - 2])))) : 0.0);
-                if (nr <= LUCKY_TAU_TWO_SIDED * S_ * vn || nl <= LUCKY_TAU_TWO_SIDED * S_ * wn) {
-                    ell_used = i;
+                if (nr <= LUCKY_TAU_TWO_SIDED * S_ * st.vn || nl <= LUCKY_TAU_TWO_SIDED * S_ * st.wn) {
+                    st.ended = true;
                     break;
                 }
-                if (cabs(delta) <= SERIOUS_TAU * nr * nl) {
-                    ell_used = i;
-                    if (tid == 0) J.status[ST_STATUS] = NKS_E_BREAKDOWN;
-                    break;
-                }
+                if (cabs(delta) <= SERIOUS_TAU * nr * nl) { st.ended = true; st.serious = true; break; }
                 const double2 beta = csqrt_principal(delta);
                 const double2 gamma = cdiv(cconj(delta), beta);
                 if (tid == 0) { bl[i - 1] = s_from<T>(beta); gl[i - 1] = s_from<T>(gamma); }
@@ -708,11 +684,11 @@ __device__ void nested_job(const JobDesc& J, double2* lds, double* ldsd, int* ld
                     v[q] = s_mul(r[q], s_from<T>(ib));
                     w[q] = s_mul(l[q], s_from<T>(ig));
                 }
-                vn = nr / cabs(beta);
-                wn = nl / cabs(gamma);
+                st.vn = nr / cabs(beta);
+                st.wn = nl / cabs(gamma);
                 __syncthreads();
-                apply_hprime<T, false>(P, k, p, v, r, scan_lds);
-                apply_hprime<T, true>(P, k, p, w, l, scan_lds);
+                apply_hprime<T, false>(P, k, p, v, r, sm.scan);
+                apply_hprime<T, true>(P, k, p, w, l, sm.scan);
                 for (int q = tid; q < k; q += NT) {
                     r[q] = s_sub(r[q], s_mul(s_from<T>(gamma), vp[q]));
                     l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(beta)), wp[q]));
@@ -720,53 +696,261 @@ __device__ void nested_job(const JobDesc& J, double2* lds, double* ldsd, int* ld
                 __syncthreads();
             }
         }
+        // step i+1: store v_{i+1}, alpha_{i+1}, r -= alpha v (l -= conj(alpha) w)
+        for (int q = tid; q < k; q += NT) vl[(size_t)i * k + q] = v[q];
         __syncthreads();
-        // ---------------------------------------------------- step 5: RHi on H_ell
-        const int n = ell_used;
-        for (int e = tid; e < n * n; e += NT) {
-            const int i = e / n, j = e - i * n;
-            T val = s_zero<T>();
-            if (i == j) val = al[i];
-            else if (i == j + 1) val = bl[j];
-            else if (j == i + 1) val = gl[i];
-            S[e] = val;
+        if (!CPLX) {
+            const double a = s_d2(block_dot<T>(v, r, k, sm.red)).x;
+            if (tid == 0) al[i] = s_from<T>(mk(a, 0.0));
+            for (int q = tid; q < k; q += NT) r[q] = s_sub(r[q], s_scale(v[q], a));
+        } else {
+            const double2 a = s_d2(block_dot<T>(w, r, k, sm.red));
+            if (tid == 0) al[i] = s_from<T>(a);
+            for (int q = tid; q < k; q += NT) {
+                r[q] = s_sub(r[q], s_mul(s_from<T>(a), v[q]));
+                l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(a)), w[q]));
+            }
         }
         __syncthreads();
-        rhi_it = rhi<T>(S, B, n, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, lds, ldsd, ldsi);
-        __syncthreads();
-        for (int j = tid; j < n; j += NT) s_e1[j] = S[(size_t)j * n];
-        __syncthreads();
-        // c = V_ell s  (into v)
-        T* c = (T*)P.v;
-        for (int q = tid; q < k; q += NT) {
-            T acc = s_zero<T>();
-            for (int j = 0; j < n; ++j) acc = s_add(acc, s_mul(vl[(size_t)j * k + q], s_e1[j]));
-            c[q] = acc;
-        }
-        __syncthreads();
-        for (int q = tid; q < k; q += NT) vl[q] = c[q];
-        __syncthreads();
+        st.i = i + 1;
     }
-    // lift weights omega_j = |b| c_j sv_j (c in vl[0..k))
-    for (int q = tid; q < k; q += NT) J.omega[q] = cscale(cmul(s_d2(vl[q]), SV[q + 1]), bnorm);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- step 5: RHi and c
+// c = V_m sgn(H_m) e_1 for the leading m x m inner Ritz matrix -> out (k)
+template <typename T>
+__device__ int inner_coeffs(const JobDesc& J, const NestPtrs& P, int k, int m, T* out, const Smem& sm) {
+    const int tid = threadIdx.x;
+    T* S = (T*)P.S;
+    T* B = (T*)P.B;
+    const T* al = (const T*)P.al;
+    const T* bl = (const T*)P.bl;
+    const T* gl = (const T*)P.gl;
+    const T* vl = (const T*)P.vl;
+    T* s_e1 = (T*)P.y;
+    for (int e = tid; e < m * m; e += NT) {
+        const int i = e / m, j = e - i * m;
+        T val = s_zero<T>();
+        if (i == j) val = al[i];
+        else if (i == j + 1) val = bl[j];
+        else if (j == i + 1) val = gl[i];
+        S[e] = val;
+    }
+    __syncthreads();
+    const int it = rhi<T>(S, B, m, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, sm.red, sm.redd, sm.redi);
+    __syncthreads();
+    for (int j = tid; j < m; j += NT) s_e1[j] = S[(size_t)j * m];
+    __syncthreads();
+    for (int q = tid; q < k; q += NT) {
+        T acc = s_zero<T>();
+        for (int j = 0; j < m; ++j) acc = s_add(acc, s_mul(vl[(size_t)j * k + q], s_e1[j]));
+        out[q] = acc;
+    }
+    __syncthreads();
+    return it;
+}
+
+// non-nested: c = sgn(H_k) e_1 by RHi on H_k itself -> out (k)
+template <typename T>
+__device__ int nonnested_coeffs(const JobDesc& J, const NestPtrs& P, int k, T* out, const Smem& sm) {
+    const int tid = threadIdx.x;
+    T* S = (T*)P.S;
+    T* B = (T*)P.B;
+    const T* d = (const T*)P.d;
+    const T* sub = (const T*)P.sub;
+    const T* sup = (const T*)P.sup;
+    for (int e = tid; e < k * k; e += NT) {
+        const int i = e / k, j = e - i * k;
+        T v = s_zero<T>();
+        if (i == j) v = d[i];
+        else if (i == j + 1) v = sub[j];
+        else if (j == i + 1) v = sup[i];
+        S[e] = v;
+    }
+    __syncthreads();
+    const int it = rhi<T>(S, B, k, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, sm.red, sm.redd, sm.redi);
+    __syncthreads();
+    for (int i = tid; i < k; i += NT) out[i] = S[(size_t)i * k];
+    __syncthreads();
+    return it;
+}
+
+template <typename T>
+__device__ double rel_change(const T* a, const T* b, int k, const Smem& sm) {   // |a - b| / |a|
+    double dn = 0.0, an = 0.0;
+    for (int i = threadIdx.x; i < k; i += NT) {
+        dn += s_abs2(s_sub(a[i], b[i]));
+        an += s_abs2(a[i]);
+    }
+    const double2 r = block_sum<NT>(mk(dn, an), sm.red);
+    return sqrt(r.x) / sqrt(r.y);
+}
+
+struct NestResult {
+    int ell = 0;        // inner size of the accepted result (0 = non-nested)
+    int rhi = 0;        // RHi iterations (negative: no convergence)
+    int status = NKS_OK;
+    double p = 0.0, zmin = 0.0, zmax = 0.0, inner_delta = 0.0;
+};
+
+// Steps 3-5 on H_k (k = kk) with the job's ell policy; the result c is left in P.cc.
+template <typename T>
+__device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk, const Smem& sm) {
+    const int tid = threadIdx.x;
+    double2* sc = J.sc;
+    const size_t st = J.scstride;
+    T* d = (T*)P.d;
+    T* sub = (T*)P.sub;
+    T* sup = (T*)P.sup;
+    for (int i = tid; i < kk; i += NT) {
+        d[i] = s_from<T>(sc[SC_ALPHA * st + i + 1]);
+        if (i + 1 < kk) { sub[i] = s_from<T>(sc[SC_BETA * st + i + 1]); sup[i] = s_from<T>(sc[SC_GAMMA * st + i + 1]); }
+    }
+    __syncthreads();
+    T* cc = (T*)P.cc;
+    T* cp = (T*)P.cp;
+    NestResult res;
+    const int cap = min(J.lcap, kk);   // largest inner size allowed
+    const bool doubling = J.ell_policy != NKS_POLICY_FIXED;
+    const int ell0 = doubling ? ELL0 : J.ell;
+    if (ell0 >= kk || (doubling && ell0 >= cap && cap >= kk)) {
+        res.rhi = nonnested_coeffs<T>(J, P, kk, cc, sm);
+        res.ell = 0;
+        return res;
+    }
+    double p = J.p;
+    if (p <= 0.0) {
+        estimate_extremes<T>(J, P, kk, sm, res.zmin, res.zmax);
+        p = 1.0 / sqrt(res.zmin * res.zmax);
+    }
+    res.p = p;
+    if (lu_pH<T>(P, kk, p) != 0) { res.status = NKS_E_NOCONV; return res; }
+    Inner in;
+    inner_init<T>(P, kk, p, in, sm);
+    if (!doubling) {
+        inner_extend<T>(P, kk, p, min(ell0, cap), in, sm);
+        res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
+        res.ell = in.i;
+    } else {
+        int ell = min(ell0, cap);
+        inner_extend<T>(P, kk, p, ell, in, sm);
+        res.rhi = inner_coeffs<T>(J, P, kk, in.i, cp, sm);
+        res.ell = in.i;
+        while (true) {
+            const int ell2 = 2 * ell;
+            if (ell2 >= cap && cap >= kk) {          // the inner space would be the whole of H_k
+                res.rhi = nonnested_coeffs<T>(J, P, kk, cc, sm);
+                res.inner_delta = rel_change<T>(cc, cp, kk, sm);
+                res.ell = 0;
+                break;
+            }
+            const int target = min(ell2, cap);
+            inner_extend<T>(P, kk, p, target, in, sm);
+            res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
+            res.ell = in.i;
+            res.inner_delta = rel_change<T>(cc, cp, kk, sm);
+            if (res.inner_delta <= J.tol / 10 || target >= cap || in.ended) break;
+            for (int i = tid; i < kk; i += NT) cp[i] = cc[i];
+            __syncthreads();
+            ell = ell2;
+        }
+    }
+    if (in.serious) res.status = NKS_E_BREAKDOWN;
+    return res;
+}
+
+enum NestMode { NEST_FINAL = 0, NEST_CHECKPOINT = 1 };
+
+template <typename T>
+__device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm) {
+    const int tid = threadIdx.x;
+    const size_t st = J.scstride;
+    const double2* SV = J.sc + SC_SV * st;
+    const double2* VN = J.sc + SC_VN * st;
+    const bool kpol = J.k_policy != NKS_POLICY_FIXED;
+    int kk;
+    if (mode == NEST_CHECKPOINT) {
+        if (!kpol || J.status[ST_DONE] || j >= J.k) return;
+        kk = j;
+    } else {
+        kk = J.status[ST_KUSED];
+        if (kk == 0) return;                              // zero source; lift writes zeros
+        if (J.status[ST_CKPT_DONE]) {                     // a checkpoint already accepted H_kk
+            return;
+        }
+    }
+    NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
+    NestResult res = nested_coeffs<T>(J, P, kk, sm);
+    const T* cc = (const T*)P.cc;
+    double outer_delta = -1.0;
+    if (kpol && J.status[ST_NCKPT] > 0 && res.status == NKS_OK) {
+        // change against the previous checkpoint, weighted by the basis norms
+        const int kprev = J.status[ST_KCKPT];
+        double dn = 0.0, cn = 0.0;
+        for (int i = tid; i < kk; i += NT) {
+            const double w2 = cabs2(VN[i + 1]);
+            const double2 ci = s_d2(cc[i]);
+            const double2 di = (i < kprev) ? csub(ci, J.ckpt[i]) : ci;
+            dn += cabs2(di) * w2;
+            cn += cabs2(ci) * w2;
+        }
+        const double2 r = block_sum<NT>(mk(dn, cn), sm.red);
+        outer_delta = sqrt(r.x) / sqrt(r.y);
+    }
+    const bool accept = mode == NEST_CHECKPOINT && outer_delta >= 0.0 && outer_delta <= J.tol / 4;
+    if (mode == NEST_CHECKPOINT && !accept) {
+        for (int i = tid; i < kk; i += NT) J.ckpt[i] = s_d2(cc[i]);
+        __syncthreads();
+        if (tid == 0) {
+            J.status[ST_KCKPT] = kk;
+            J.status[ST_NCKPT] += 1;
+            J.report[RP_OUTER_DELTA] = outer_delta;
+        }
+        return;
+    }
+    // final result (or an accepted checkpoint): lift weights omega_j = |b| c_j sv_j
+    const double bnorm = J.report[RP_BNORM];
+    for (int q = tid; q < kk; q += NT) J.omega[q] = cscale(cmul(s_d2(cc[q]), SV[q + 1]), bnorm);
     if (tid == 0) {
-        if (rhi_it < 0 && J.status[ST_STATUS] == NKS_OK) J.status[ST_STATUS] = NKS_E_NOCONV;
-        J.status[ST_ELL] = ell_used;
-        J.status[ST_RHI] = rhi_it < 0 ? -rhi_it : rhi_it;
-        J.report[RP_P] = p_used;
-        J.report[RP_ZMIN] = zmin;
-        J.report[RP_ZMAX] = zmax;
+        if (accept) {
+            J.status[ST_DONE] = 1;
+            J.status[ST_KUSED] = kk;
+            J.status[ST_CKPT_DONE] = 1;
+        }
+        int status = J.status[ST_STATUS];
+        if (status == NKS_OK && res.status != NKS_OK) status = res.status;
+        if (status == NKS_OK && res.rhi < 0) status = NKS_E_NOCONV;
+        if (status == NKS_OK && J.ell_policy != NKS_POLICY_FIXED && res.inner_delta > J.tol / 10)
+            status = NKS_E_NOCONV;
+        // k policy that ran to its cap without meeting tol (a lucky breakdown is exact)
+        if (status == NKS_OK && kpol && !accept && J.status[ST_DONE] == 0 &&
+            (outer_delta < 0.0 || outer_delta > J.tol / 4))
+            status = NKS_E_NOCONV;
+        J.status[ST_STATUS] = status;
+        J.status[ST_ELL] = res.ell;
+        J.status[ST_RHI] = res.rhi < 0 ? -res.rhi : res.rhi;
+        J.report[RP_P] = res.p;
+        J.report[RP_ZMIN] = res.zmin;
+        J.report[RP_ZMAX] = res.zmax;
+        J.report[RP_INNER_DELTA] = res.inner_delta;
+        if (outer_delta >= 0.0) J.report[RP_OUTER_DELTA] = outer_delta;
     }
 }
 
-__global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs) {
-    __shared__ double2 lds[NT / 64];
-    __shared__ double ldsd[NT / 64];
-    __shared__ int ldsi[NT / 64];
+__global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int j) {
+    __shared__ double2 red[NT / 64];
+    __shared__ double redd[NT / 64];
+    __shared__ int redi[NT / 64];
     __shared__ Aff2<double2> scan_lds[NT];
+    Smem sm;
+    sm.red = red;
+    sm.redd = redd;
+    sm.redi = redi;
+    sm.scan = scan_lds;
     const JobDesc& J = jobs[blockIdx.x];
-    if (J.two_sided) nested_job<double2>(J, lds, ldsd, ldsi, scan_lds);
-    else nested_job<double>(J, lds, ldsd, ldsi, scan_lds);
+    if (J.two_sided) nested_job<double2>(J, mode, j, sm);
+    else nested_job<double>(J, mode, j, sm);
 }
 
 // H(k,k) = alpha_k from the partial sums of the last stencil pass (the
@@ -795,7 +979,11 @@ void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s) {
 }
 
 void launch_nested(JobDesc* jobs, int njobs, hipStream_t s) {
-    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs);
+    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_FINAL, 0);
+}
+
+void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s) {
+    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_CHECKPOINT, j);
 }
 
 }  // namespace nks

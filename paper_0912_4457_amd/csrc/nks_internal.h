@@ -89,6 +89,9 @@ enum StatusWord {
     ST_BDITER = 3,      // serious breakdown iteration
     ST_ELL = 4,         // inner size used (0 = non-nested)
     ST_RHI = 5,         // RHi iterations
+    ST_CKPT_DONE = 6,   // a k-checkpoint accepted the result (omega already written)
+    ST_NCKPT = 7,       // k-checkpoints stored so far
+    ST_KCKPT = 8,       // size of the stored checkpoint coefficients
     ST_COUNT = 16
 };
 
@@ -129,7 +132,13 @@ struct JobDesc {
     int scstride;       // length of each scalar slot (kcap + 2)
     int nblocks;        // blocks per job of the outer site-parallel kernels
     int precision;      // NKS_FP64 / NKS_MIXED
+    int k_policy;       // NKS_POLICY_*
+    int ell_policy;
+    double tol;         // target relative accuracy of the policies
+    double2* ckpt;      // coefficients of the last k-checkpoint (kcap)
 };
+
+constexpr int CKPT_DK = 100;   // outer iterations between k-checkpoints
 
 // ----------------------------------------------------------------- reductions
 __device__ inline double2 shfl_xor_d2(double2 v, int m) {
@@ -167,6 +176,12 @@ template <typename R>
 void launch_apply(const Geom& g, const cx_t<R>* links, double kappa, double mu, const double2* in,
                   double2* out, cx_t<R>* tmp_in, cx_t<R>* tmp_out, hipStream_t s);
 
+// Launch-shape choices of the outer passes (picked per context; see api.hip).
+struct Tuning {
+    int xcd_map = 1;      // 1D grid mapped so that all jobs of a site block run on one XCD
+    int split_dual = 1;   // two-sided stencil: A u and A^dagger t in separate blocks
+};
+
 // outer.hip
 struct OuterLaunch {
     Geom g;
@@ -178,6 +193,7 @@ struct OuterLaunch {
     int nblocks;          // blocks per job of the site-parallel kernels
     int precision;        // NKS_FP64 / NKS_MIXED
     int two_sided;
+    Tuning tune;
 };
 constexpr int OUTER_NT = 128;
 void launch_pack(const OuterLaunch& L, hipStream_t s);
@@ -189,6 +205,7 @@ void launch_lift(const OuterLaunch& L, hipStream_t s);
 constexpr int NEST_NT = 256;
 void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s);
 void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
+void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // after R_j
 size_t nest_words(int k, int ell, int two_sided);
 
 }  // namespace nks

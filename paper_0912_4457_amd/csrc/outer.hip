@@ -38,6 +38,23 @@ __device__ inline cx_t<R>* lvec(const JobDesc& J, int j, int n) {     // t_j in 
     return reinterpret_cast<cx_t<R>*>(J.lring) + (size_t)(j & 1) * n;
 }
 
+// Block -> (site block, job).  With xcd_map the grid is 1D and padded to a
+// multiple of 8; the hardware hands workgroup b to XCD b % 8, so giving each
+// XCD a contiguous range of (site block, job) pairs, jobs innermost, keeps a
+// site block's links and neighbour spinors in one XCD's L2 while all jobs
+// sweep it.  Returns false for padding blocks.
+__device__ inline bool block_coords(int nblocks, int njobs, int xcd_map, int& sb, int& job) {
+    if (!xcd_map) { sb = blockIdx.x; job = blockIdx.y; return true; }
+    const int total = nblocks * njobs;
+    const int per = (total + 7) / 8;
+    const int b = blockIdx.x;
+    const int q = (b & 7) * per + (b >> 3);
+    if (q >= total) return false;
+    sb = q / njobs;
+    job = q - sb * njobs;
+    return true;
+}
+
 // ------------------------------------------------------------------ pack
 template <typename R>
 __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblocks) {
@@ -70,12 +87,14 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
 // ------------------------------------------------------------------ Hermitian step
 template <typename R>
 __global__ __launch_bounds__(NT) void herm_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
-                                            double kappa, int j, int nblocks) {
-    const JobDesc& J = jobs[blockIdx.y];
+                                            double kappa, int j, int nblocks, int njobs, int xcd_map) {
+    int sb, job;
+    if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
+    const JobDesc& J = jobs[job];
     if (j > J.k || J.status[ST_DONE]) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
-    const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
+    const bool b0 = (sb == 0 && threadIdx.x == 0);
     // beta_{j-1} (or |b| when j == 1) from the previous kernel's partial sums
     const double beta = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
     double svj, cprev;
@@ -103,7 +122,7 @@ __global__ __launch_bounds__(NT) void herm_S(JobDesc* jobs, Geom g, const cx_t<R
             slot(J, SC_VN)[j] = mk(1.0, 0.0);
         }
     }
-    const int site = blockIdx.x * NT + threadIdx.x;
+    const int site = sb * NT + threadIdx.x;
     double part = 0.0;
     if (site < g.V) {
         const cx_t<R>* uj = column<R>(J, j, n);
@@ -127,20 +146,22 @@ __global__ __launch_bounds__(NT) void herm_S(JobDesc* jobs, Geom g, const cx_t<R
         }
     }
     const double2 s = block_sum<NT>(mk(part, 0.0), lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + sb] = s;
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nblocks) {
-    const JobDesc& J = jobs[blockIdx.y];
+__global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map) {
+    int sb, job;
+    if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
+    const JobDesc& J = jobs[job];
     if (j >= J.k || J.status[ST_DONE]) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * V;
     const double svj = slot(J, SC_SV)[j].x;
     const double alpha = svj * sum_partials<NT>(J.part + (size_t)PS_S * nblocks, nblocks, lds).x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = mk(alpha, 0.0);
+    if (sb == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = mk(alpha, 0.0);
     const double cu = alpha * svj;
-    const int site = blockIdx.x * NT + threadIdx.x;
+    const int site = sb * NT + threadIdx.x;
     double nr2 = 0.0;
     if (site < V) {
         const cx_t<R>* uj = column<R>(J, j, n);
@@ -155,18 +176,24 @@ __global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nb
         }
     }
     const double2 s = block_sum<NT>(mk(nr2, 0.0), lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + sb] = s;
 }
 
 // ------------------------------------------------------------------ two-sided step
-template <typename R>
+// SPLIT = false: one thread computes A u_j and A^dagger t_j (links loaded once).
+// SPLIT = true: blockIdx.z selects the field (0: A u_j, 1: A^dagger t_j), which
+// halves the registers of a thread; the links are then shared through the caches.
+template <typename R, bool SPLIT>
 __global__ __launch_bounds__(NT) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
-                                          double kappa, double mu, int j, int nblocks) {
-    const JobDesc& J = jobs[blockIdx.y];
+                                          double kappa, double mu, int j, int nblocks, int njobs, int xcd_map) {
+    int sb, job;
+    if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
+    const JobDesc& J = jobs[job];
     if (j > J.k || J.status[ST_DONE]) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
-    const bool b0 = (blockIdx.x == 0 && threadIdx.x == 0);
+    const int field = SPLIT ? (int)blockIdx.z : 0;
+    const bool b0 = (sb == 0 && threadIdx.x == 0 && field == 0);
     double2 sv, sw, cv, cw;   // v_j = sv u_j, w_j = sw t_j; subtract cv u_{j-1}, cw t_{j-1}
     if (j == 1) {
         const double bn = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
@@ -213,50 +240,81 @@ __global__ __launch_bounds__(NT) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>*
             slot(J, SC_WN)[j] = mk(nl / cabs(gamma), 0.0);
         }
     }
-    const int site = blockIdx.x * NT + threadIdx.x;
+    const int site = sb * NT + threadIdx.x;
     double2 part = mk(0.0, 0.0);
     if (site < g.V) {
         const cx_t<R>* uj = column<R>(J, j, n);
         const cx_t<R>* tj = lvec<R>(J, j, n);
-        R cf[2][4], cb[2][4];
-        hop_coefs<R>(kappa, mu, cf[0], cb[0]);     // A
-        hop_coefs<R>(kappa, -mu, cf[1], cb[1]);    // A^dagger = A(-mu)
-        const cx_t<R>* const fields[2] = {uj, tj};
-        cx_t<R> acc[2][12];
-        wilson_site<R, 2>(g, links, fields, cf, cb, site, acc);
         const cx_t<R>* up = (j >= 2) ? column<R>(J, j - 1, n) : nullptr;
         cx_t<R>* tl = lvec<R>(J, j + 1, n);        // holds t_{j-1}; overwritten by l (own site only)
         cx_t<R>* rout = (j < J.k) ? column<R>(J, j + 1, n) : nullptr;
+        if constexpr (!SPLIT) {
+            R cf[2][4], cb[2][4];
+            hop_coefs<R>(kappa, mu, cf[0], cb[0]);     // A
+            hop_coefs<R>(kappa, -mu, cf[1], cb[1]);    // A^dagger = A(-mu)
+            const cx_t<R>* const fields[2] = {uj, tj};
+            cx_t<R> acc[2][12];
+            wilson_site<R, 2>(g, links, fields, cf, cb, site, acc);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const size_t e = (size_t)c * g.V + site;
-            double2 r = cmul(sv, to_d2<R>(acc[0][c]));
-            double2 l = cmul(sw, to_d2<R>(acc[1][c]));
-            if (up) {
-                r = csub(r, cmul(cv, to_d2<R>(up[e])));
-                l = csub(l, cmul(cw, to_d2<R>(tl[e])));
+            for (int c = 0; c < 12; ++c) {
+                const size_t e = (size_t)c * g.V + site;
+                double2 r = cmul(sv, to_d2<R>(acc[0][c]));
+                double2 l = cmul(sw, to_d2<R>(acc[1][c]));
+                if (up) {
+                    r = csub(r, cmul(cv, to_d2<R>(up[e])));
+                    l = csub(l, cmul(cw, to_d2<R>(tl[e])));
+                }
+                const cx_t<R> rs = from_d2<R>(r);
+                if (rout) { rout[e] = rs; tl[e] = from_d2<R>(l); }
+                part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
             }
-            const cx_t<R> rs = from_d2<R>(r);
-            if (rout) { rout[e] = rs; tl[e] = from_d2<R>(l); }
-            part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
+        } else {
+            R cf[1][4], cb[1][4];
+            hop_coefs<R>(kappa, field == 0 ? mu : -mu, cf[0], cb[0]);
+            const cx_t<R>* const fields[1] = {field == 0 ? uj : tj};
+            cx_t<R> acc[1][12];
+            wilson_site<R, 1>(g, links, fields, cf, cb, site, acc);
+            if (field == 0) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t e = (size_t)c * g.V + site;
+                    double2 r = cmul(sv, to_d2<R>(acc[0][c]));
+                    if (up) r = csub(r, cmul(cv, to_d2<R>(up[e])));
+                    const cx_t<R> rs = from_d2<R>(r);
+                    if (rout) rout[e] = rs;
+                    part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
+                }
+            } else if (rout) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const size_t e = (size_t)c * g.V + site;
+                    double2 l = cmul(sw, to_d2<R>(acc[0][c]));
+                    if (up) l = csub(l, cmul(cw, to_d2<R>(tl[e])));
+                    tl[e] = from_d2<R>(l);
+                }
+            }
         }
     }
-    const double2 s = block_sum<NT>(part, lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + blockIdx.x] = s;
+    if (field == 0) {
+        const double2 s = block_sum<NT>(part, lds);
+        if (threadIdx.x == 0) J.part[(size_t)PS_S * nblocks + sb] = s;
+    }
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblocks) {
-    const JobDesc& J = jobs[blockIdx.y];
+__global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map) {
+    int sb, job;
+    if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
+    const JobDesc& J = jobs[job];
     if (j >= J.k || J.status[ST_DONE]) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * V;
     const double2 sv = slot(J, SC_SV)[j], sw = slot(J, SC_SW)[j];
     const double2 alpha = cmul(cconj(sw), sum_partials<NT>(J.part + (size_t)PS_S * nblocks, nblocks, lds));
-    if (blockIdx.x == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = alpha;
+    if (sb == 0 && threadIdx.x == 0) slot(J, SC_ALPHA)[j] = alpha;
     const double2 cu = cmul(alpha, sv);                 // alpha v_j = cu u_j
     const double2 ct = cmul(cconj(alpha), sw);          // conj(alpha) w_j = ct t_j
-    const int site = blockIdx.x * NT + threadIdx.x;
+    const int site = sb * NT + threadIdx.x;
     double2 d = mk(0.0, 0.0);
     double nr2 = 0.0, nl2 = 0.0;
     if (site < V) {
@@ -278,11 +336,11 @@ __global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblo
         }
     }
     double2 s = block_sum<NT>(d, lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + sb] = s;
     s = block_sum<NT>(mk(nr2, 0.0), lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_R1 * nblocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) J.part[(size_t)PS_R1 * nblocks + sb] = s;
     s = block_sum<NT>(mk(nl2, 0.0), lds);
-    if (threadIdx.x == 0) J.part[(size_t)PS_R2 * nblocks + blockIdx.x] = s;
+    if (threadIdx.x == 0) J.part[(size_t)PS_R2 * nblocks + sb] = s;
 }
 
 // ------------------------------------------------------------------ lift
@@ -319,32 +377,47 @@ void launch_pack(const OuterLaunch& L, hipStream_t s) {
         hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
 }
 
-void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s) {
-    dim3 grid(L.nblocks, L.njobs);
-    if (L.precision == NKS_FP64) {
-        auto links = static_cast<const double2*>(L.links);
-        if (!L.two_sided)
-            hipLaunchKernelGGL(herm_S<double>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks);
-        else
-            hipLaunchKernelGGL(bi_S<double>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j, L.nblocks);
+static dim3 outer_grid(const OuterLaunch& L, int z) {
+    if (L.tune.xcd_map) {
+        const int total = L.nblocks * L.njobs;
+        return dim3(8 * ((total + 7) / 8), 1, z);
+    }
+    return dim3(L.nblocks, L.njobs, z);
+}
+
+template <typename R>
+static void outer_S(const OuterLaunch& L, int j, hipStream_t s) {
+    auto links = static_cast<const cx_t<R>*>(L.links);
+    const int xm = L.tune.xcd_map;
+    if (!L.two_sided) {
+        hipLaunchKernelGGL(herm_S<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks,
+                           L.njobs, xm);
+    } else if (L.tune.split_dual) {
+        hipLaunchKernelGGL((bi_S<R, true>), outer_grid(L, 2), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j,
+                           L.nblocks, L.njobs, xm);
     } else {
-        auto links = static_cast<const float2*>(L.links);
-        if (!L.two_sided)
-            hipLaunchKernelGGL(herm_S<float>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks);
-        else
-            hipLaunchKernelGGL(bi_S<float>, grid, dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j, L.nblocks);
+        hipLaunchKernelGGL((bi_S<R, false>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j,
+                           L.nblocks, L.njobs, xm);
     }
 }
 
+template <typename R>
+static void outer_R(const OuterLaunch& L, int j, hipStream_t s) {
+    const int xm = L.tune.xcd_map;
+    if (!L.two_sided)
+        hipLaunchKernelGGL(herm_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm);
+    else
+        hipLaunchKernelGGL(bi_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm);
+}
+
+void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s) {
+    if (L.precision == NKS_FP64) outer_S<double>(L, j, s);
+    else outer_S<float>(L, j, s);
+}
+
 void launch_outer_R(const OuterLaunch& L, int j, hipStream_t s) {
-    dim3 grid(L.nblocks, L.njobs);
-    if (L.precision == NKS_FP64) {
-        if (!L.two_sided) hipLaunchKernelGGL(herm_R<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
-        else hipLaunchKernelGGL(bi_R<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
-    } else {
-        if (!L.two_sided) hipLaunchKernelGGL(herm_R<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
-        else hipLaunchKernelGGL(bi_R<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks);
-    }
+    if (L.precision == NKS_FP64) outer_R<double>(L, j, s);
+    else outer_R<float>(L, j, s);
 }
 
 void launch_lift(const OuterLaunch& L, hipStream_t s) {

@@ -108,3 +108,49 @@ def test_batch_equals_single_calls_bitwise():
         y, s1 = nks.sign_apply(j["lat"], j["b"], k=j["k"], ell=j["ell"], p=j["p"])
         assert np.array_equal(to_np(x), to_np(y))
         assert st["k_used"] == s1["k_used"]
+
+
+def test_tuning_choices_are_bitwise_identical():
+    # every launch shape the autotuner can pick gives the same bits
+    import paper_0912_4457_amd as nks
+    from gpu_common import ctx
+    c = ctx()
+    la = lattice((4, 4, 4, 6), 0.5, 21, 0.0)
+    lb = lattice((4, 4, 4, 6), 0.5, 21, 0.25)
+    jobs = [dict(lat=la, b=I.gaussian_source((4, 4, 4, 6), 5).ravel(), k=80, ell=20),
+            dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=80, ell=20),
+            dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20)]
+    ref = None
+    try:
+        for xm in (0, 1):
+            for sd in (0, 1):
+                c.tune_set("xcd_map", xm)
+                c.tune_set("split_dual", sd)
+                xs, _ = nks.sign_apply_batch(jobs)
+                got = [to_np(x) for x in xs]
+                if ref is None:
+                    ref = got
+                else:
+                    for a, b in zip(got, ref):
+                        assert np.array_equal(a, b)
+    finally:
+        c.tune_set("xcd_map", 1)
+        c.tune_set("split_dual", 1)
+
+
+def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
+    import paper_0912_4457_amd as nks
+    from paper_0912_4457_amd import autotune
+    from gpu_common import ctx
+    monkeypatch.setenv("NKS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    c = ctx()
+    lb = lattice((4, 4, 4, 6), 0.5, 21, 0.25)
+    jobs = [dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=40, ell=10)]
+    res = autotune.autotune(c, jobs, k_probe=16)
+    assert set(res["choice"]) == {"xcd_map", "split_dual"}
+    assert len(res["timings"]) == 4
+    assert c.tune_get("split_dual") == res["choice"]["split_dual"]
+    again = autotune.autotune(c, jobs, k_probe=16)     # cached
+    assert again["choice"] == res["choice"]
+    c.tune_set("xcd_map", 1)
+    c.tune_set("split_dual", 1)

@@ -218,3 +218,33 @@ def test_pure_gauge_nested_full_method():
         ref = closedform.pure_gauge_sign_apply(b, g, dims, M0, mu)
         y, info = nested.sign_apply(op, b, 200, 80)
         assert nested.rel_err(y, ref) < 1e-10
+
+
+# ---------------------------------------------------------------- plain ell / k policy
+def test_ell_doubling_meets_its_tolerance():
+    from oracle import policy
+    op = _op(0.0)
+    kr = krylov.lanczos(op.matvec, I.gaussian_source(op.dims, 7).ravel(), 240)
+    c_nn, _ = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, True, 240)
+    for tol in (1e-4, 1e-8, 1e-11):
+        c, info = policy.ell_doubling(kr.alpha, kr.beta, kr.gamma, True, tol)
+        assert info["inner_delta"] <= tol / 10 or not info["nested"]
+        assert np.linalg.norm(c - c_nn) <= tol * np.linalg.norm(c_nn)
+    # tighter tolerance never needs a smaller ell
+    ells = [policy.ell_doubling(kr.alpha, kr.beta, kr.gamma, True, t)[1]["ell"] for t in (1e-3, 1e-6, 1e-10)]
+    assert ells == sorted(ells)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_k_checkpoint_policy_reaches_tolerance(mu):
+    from oracle import policy
+    op = _op(mu)
+    b = I.gaussian_source(op.dims, 8)
+    ref = _exact(op, b)
+    ks = []
+    for tol in (1e-5, 1e-9):
+        y, info = policy.sign_apply_policy(op, b, tol, k_max=600, dk=40)
+        assert info["converged"]
+        assert nested.rel_err(y, ref) <= 10 * tol
+        ks.append(info["k"])
+    assert ks[0] < ks[1]
