@@ -182,6 +182,22 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
                     const double* gamma_host, int hermitian, const nks_opts* opts,
                     double* c_host, nks_stats* stats);
 
+/* Predictor network of the learned ell/k policy: MLP 16 -> 64 -> 64 -> 2
+ * with SiLU, parameters as one float32 vector of NKS_MLP_NPARAMS entries
+ * (W1[16][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2]; z = h W + b).
+ * Products run on bf16 MFMA with bfloat16 operands (round to nearest even)
+ * and float32 accumulation.  All pointers are device pointers; x is
+ * [batch][16], y and t are [batch][2].  Asynchronous on the stream. */
+#define NKS_MLP_NPARAMS 5378
+int nks_mlp_forward(nks_ctx* ctx, const float* params, const float* x, int batch, float* y, void* stream);
+/* grad = gradient of 0.5 * mean_b ||y_b - t_b||^2; *loss = that loss. */
+int nks_mlp_backward(nks_ctx* ctx, const float* params, const float* x, const float* t, int batch,
+                     float* grad, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on params with moments
+ * m, v; step counts from 1. */
+int nks_mlp_adam_step(nks_ctx* ctx, float* params, const float* grad, float* m, float* v, int step,
+                      float lr, void* stream);
+
 /* Launch-shape choices of the outer passes, per context (an autotuner sets
  * them after timing the alternatives):
  *   "xcd_map"    1: 1D grid that keeps every job of a site block on one XCD

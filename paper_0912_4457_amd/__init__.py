@@ -88,6 +88,9 @@ SIGNATURES = {
     "nks_outer_basis": (_I, [_VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, _PD, _PD, _PD,
                              ctypes.POINTER(Stats)]),
     "nks_nested_step": (_I, [_VP, _I, _PD, _PD, _PD, _I, ctypes.POINTER(Opts), _PD, ctypes.POINTER(Stats)]),
+    "nks_mlp_forward": (_I, [_VP, _VP, _VP, _I, _VP, _VP]),
+    "nks_mlp_backward": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _VP]),
+    "nks_mlp_adam_step": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.c_float, _VP]),
     "nks_tune_set": (_I, [_VP, ctypes.c_char_p, _I]),
     "nks_tune_get": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
     "nks_profile_enable": (_I, [_VP, _I]),
@@ -349,6 +352,42 @@ def outer_basis(lat: Lattice, b, k: int, precision="fp64"):
     bb = bb.view(np.complex128)[:max(ku - 1, 0)]
     g = g.view(np.complex128)[:max(ku - 1, 0)]
     return a, bb, g, st.as_dict()
+
+
+MLP_NPARAMS = 5378
+
+
+def _f32(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.float32))
+    return t.to(device="cuda", dtype=torch.float32).contiguous()
+
+
+def mlp_forward(ctx: Context, params, x):
+    """y = MLP(x) for x of shape (batch, 16); params: float32 vector of 5378."""
+    torch = _torch()
+    params, x = _f32(params), _f32(x)
+    y = torch.empty((x.shape[0], 2), dtype=torch.float32, device=x.device)
+    ctx.check(lib().nks_mlp_forward(ctx.h, params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr(), _stream()))
+    return y
+
+
+def mlp_backward(ctx: Context, params, x, t):
+    """(loss, grad) of 0.5 * mean ||MLP(x) - t||^2."""
+    torch = _torch()
+    params, x, t = _f32(params), _f32(x), _f32(t)
+    g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    ctx.check(lib().nks_mlp_backward(ctx.h, params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0], g.data_ptr(),
+                                     loss.data_ptr(), _stream()))
+    return loss, g
+
+
+def mlp_adam_step(ctx: Context, params, grad, m, v, step: int, lr: float):
+    """In-place Adam update of the float32 tensors params, m, v."""
+    ctx.check(lib().nks_mlp_adam_step(ctx.h, params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                      int(step), float(lr), _stream()))
 
 
 def nested_step(ctx: Context, alpha, beta, gamma, hermitian: bool, ell: int, p: float | None = None,

@@ -646,6 +646,30 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
     return NKS_OK;
 }
 
+int nks_mlp_forward(nks_ctx* ctx, const float* params, const float* x, int batch, float* y, void* stream) {
+    if (!ctx || !params || !x || !y || batch < 1) return fail(ctx, NKS_E_INVALID, "bad nks_mlp_forward arguments");
+    launch_mlp_forward(params, x, batch, y, static_cast<hipStream_t>(stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return NKS_OK;
+}
+
+int nks_mlp_backward(nks_ctx* ctx, const float* params, const float* x, const float* t, int batch, float* grad,
+                     float* loss, void* stream) {
+    if (!ctx || !params || !x || !t || !grad || !loss || batch < 1)
+        return fail(ctx, NKS_E_INVALID, "bad nks_mlp_backward arguments");
+    launch_mlp_backward(params, x, t, batch, grad, loss, static_cast<hipStream_t>(stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return NKS_OK;
+}
+
+int nks_mlp_adam_step(nks_ctx* ctx, float* params, const float* grad, float* m, float* v, int step, float lr,
+                      void* stream) {
+    if (!ctx || !params || !grad || !m || !v || step < 1) return fail(ctx, NKS_E_INVALID, "bad nks_mlp_adam_step arguments");
+    launch_mlp_adam(params, grad, m, v, step, lr, static_cast<hipStream_t>(stream));
+    HIP_TRY(ctx, hipGetLastError());
+    return NKS_OK;
+}
+
 int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
     if (!ctx || !key) return NKS_E_INVALID;
     const std::string k(key);

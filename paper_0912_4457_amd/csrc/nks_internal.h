@@ -208,4 +208,11 @@ void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // after R_j
 size_t nest_words(int k, int ell, int two_sided);
 
+// mlp.hip
+int mlp_nparams();
+void launch_mlp_forward(const float* P, const float* X, int B, float* Y, hipStream_t s);
+void launch_mlp_backward(const float* P, const float* X, const float* T, int B, float* G, float* loss,
+                         hipStream_t s);
+void launch_mlp_adam(float* P, const float* G, float* M, float* V, int t, float lr, hipStream_t s);
+
 }  // namespace nks
