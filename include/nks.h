@@ -74,8 +74,8 @@ enum nks_policy {
     NKS_POLICY_DOUBLING = 1,  /* ell: double from 16 until the coefficient change
                                  is <= tol/10; k: checkpoints every 100 steps until
                                  the change is <= tol/4 (k stays <= opts.k) */
-    NKS_POLICY_LEARNED = 2    /* predicted by the loaded MLP, verified by one
-                                 doubling step, falls back to DOUBLING */
+    NKS_POLICY_LEARNED = 2    /* predicted by the network of nks_policy_load
+                                 (see there), verified, falls back to DOUBLING */
 };
 
 /* Options of one sign application.  Initialise with nks_opts_default(). */
@@ -197,6 +197,57 @@ int nks_mlp_backward(nks_ctx* ctx, const float* params, const float* x, const fl
  * m, v; step counts from 1. */
 int nks_mlp_adam_step(nks_ctx* ctx, float* params, const float* grad, float* m, float* v, int step,
                       float lr, void* stream);
+
+/* Learned ell/k policy (NKS_POLICY_LEARNED; not part of the paper).
+ *
+ * After R_{k0} (k0 = NKS_LEARN_K0 outer steps) the nested kernel computes
+ * NKS_POLICY_NFEAT features of the Ritz matrix H_{k0}:
+ *   f0 = 1, f1 = log10 zmin(H_{k0}), f2 = log10 zmax(H_{k0}),
+ *   f3 = log10 zmin(H_{k0/2}), f4 = log10(zmax/zmin), f5 = mu, f6 = log10 tol,
+ *   f7 = 1 for the two-sided recurrence else 0, f8 = log10 V,
+ *   f9 = mean |alpha_i|, f10 = mean sqrt|beta_i gamma_i|, f11..f15 = 0
+ * (zmin, zmax: smallest and largest |Ritz value|, the estimates used for
+ * p_opt), normalises them, and evaluates the network (bf16 weights and
+ * layer inputs, float32 accumulation) for t = (log10 k*, log10 ell*).
+ * The k policy stops at k_t = k* rounded up to a multiple of
+ * NKS_LABEL_DK (at least k0 + 20, else no target) and accepts H_{k_t}
+ * if the weighted coefficient change against H_{k_t - 40} is <= tol/4;
+ * otherwise it continues with the checkpoints of NKS_POLICY_DOUBLING.  The
+ * ell policy starts its doubling at the power of two >= ell* (>= 8), with
+ * the DOUBLING acceptance rule.  A learned policy on a job with k <= k0 + 20
+ * behaves as DOUBLING.
+ *
+ * nks_policy_load copies a network to the device, for every later call
+ * on ctx.  blob (host) holds NKS_POLICY_NFLOATS float32 values:
+ * [NKS_MLP_NPARAMS parameters][16 feature means][16 feature scales]
+ * [2 target means][2 target scales]; x_i = (f_i - mean_i) / scale_i and
+ * t = y * scale + mean.  Scales must be > 0 and every value finite
+ * (NKS_E_INVALID).  Waits for the device before it replaces a network. */
+#define NKS_POLICY_NFEAT 16
+#define NKS_POLICY_NFLOATS (NKS_MLP_NPARAMS + 2 * NKS_POLICY_NFEAT + 4)
+#define NKS_LEARN_K0 100
+int nks_policy_load(nks_ctx* ctx, const float* blob, int nfloats);
+
+/* Training labels for the learned policy.  Runs each job's outer loop to
+ * opts.k (FIXED policies only, else NKS_E_INVALID; x may be NULL) and
+ * writes NKS_LABEL_WORDS doubles per job (labels_host[job][word], host):
+ *   [0, 16)    the features above at k0 (f6 from opts.tol),
+ *   [16, 76)   e_i, i < NKS_LABEL_NK: weighted relative change
+ *              ||c(k_i) - c_ref||_w / ||c_ref||_w with k_i = 20 (i + 1), where
+ *              c(k) is the nested result on H_k (ell doubled from 16 to a
+ *              1e-13 change) and c_ref the same on H_{k_used};
+ *              ||d||_w^2 = sum_i |d_i|^2 ||v_{i+1}||^2 (NaN for k_i > k_used),
+ *   [76, 316)  for each k_i, the relative coefficient change of the ell
+ *              doublings 16->32, 32->64, 64->128, 128->256 (NaN once the
+ *              doubling stopped).
+ * Every k_i runs in a workgroup of its own with its own scratch (about
+ * 61 times the nested scratch of a sign application per job).
+ * Allocates its own workspace, uses the null stream and waits. */
+#define NKS_LABEL_NK 60
+#define NKS_LABEL_NELL 4
+#define NKS_LABEL_DK 20
+#define NKS_LABEL_WORDS (NKS_POLICY_NFEAT + NKS_LABEL_NK * (1 + NKS_LABEL_NELL))
+int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* labels_host);
 
 /* Launch-shape choices of the outer passes, per context (an autotuner sets
  * them after timing the alternatives):

@@ -22,7 +22,8 @@ import numpy as np
 __all__ = [
     "FP64", "MIXED", "POLICY_FIXED", "POLICY_DOUBLING", "POLICY_LEARNED",
     "NKSError", "lib", "Context", "Lattice", "apply_op", "sign_apply", "sign_apply_batch",
-    "outer_basis", "nested_step", "workspace_size", "LIB_PATH",
+    "outer_basis", "nested_step", "workspace_size", "LIB_PATH", "policy_load", "policy_label",
+    "mlp_forward", "mlp_backward", "mlp_adam_step",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnks.so")
@@ -91,6 +92,8 @@ SIGNATURES = {
     "nks_mlp_forward": (_I, [_VP, _VP, _VP, _I, _VP, _VP]),
     "nks_mlp_backward": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _VP]),
     "nks_mlp_adam_step": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.c_float, _VP]),
+    "nks_policy_load": (_I, [_VP, _VP, _I]),
+    "nks_policy_label": (_I, [_VP, _I, ctypes.POINTER(Job), _PD]),
     "nks_tune_set": (_I, [_VP, ctypes.c_char_p, _I]),
     "nks_tune_get": (_I, [_VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
     "nks_profile_enable": (_I, [_VP, _I]),
@@ -355,6 +358,35 @@ def outer_basis(lat: Lattice, b, k: int, precision="fp64"):
 
 
 MLP_NPARAMS = 5378
+POLICY_NFEAT = 16
+POLICY_NFLOATS = MLP_NPARAMS + 2 * POLICY_NFEAT + 4
+LEARN_K0 = 100
+LABEL_NK, LABEL_NELL, LABEL_DK = 60, 4, 20
+LABEL_WORDS = POLICY_NFEAT + LABEL_NK * (1 + LABEL_NELL)
+
+
+def policy_load(ctx: Context, blob):
+    """Load the learned-policy network (float32 vector of POLICY_NFLOATS:
+    parameters, feature mean/scale, target mean/scale) for later calls."""
+    blob = np.ascontiguousarray(blob, dtype=np.float32).ravel()
+    ctx.check(lib().nks_policy_load(ctx.h, blob.ctypes.data, int(blob.size)))
+
+
+def policy_label(jobs):
+    """Training labels for the learned policy; jobs: list of dicts {lat, b, k,
+    ell, tol, precision}.  Returns a (njobs, LABEL_WORDS) float64 array laid
+    out as documented for nks_policy_label."""
+    spec = []
+    for j in jobs:
+        lat = j["lat"]
+        o = make_opts(k=j.get("k", 600), ell=j.get("ell", 256), tol=j.get("tol", 1e-8),
+                      precision=j.get("precision", "fp64"))
+        spec.append((lat, _vec(lat, j["b"]), None, o))
+    ctx = spec[0][0].ctx
+    arr, keep = _job_array(spec)
+    out = np.zeros((len(spec), LABEL_WORDS))
+    ctx.check(lib().nks_policy_label(ctx.h, len(spec), arr, out.ctypes.data_as(_PD)))
+    return out
 
 
 def _f32(t):

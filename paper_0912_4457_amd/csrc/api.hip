@@ -31,6 +31,7 @@ struct nks_ctx {
     std::vector<ProfRecord> pending;
     long long prof_count[NKS_K_COUNT] = {0, 0, 0, 0};
     Tuning tune;
+    PolicyNet* net = nullptr;     // device copy of the learned-policy network (nks_policy_load)
 };
 
 struct nks_lattice {
@@ -82,7 +83,10 @@ struct JobPlan {
     int nblocks, lcap;
     int k_policy, ell_policy;
     double tol;
-    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_nest, end;
+    bool label;         // label run (nks_policy_label): checkpoint buffer + label words
+    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
+        end;
+    bool learned() const { return k_policy == NKS_POLICY_LEARNED || ell_policy == NKS_POLICY_LEARNED; }
 };
 
 struct Plan {
@@ -101,15 +105,17 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
         return fail(ctx, NKS_E_INVALID, "unknown precision");
     if (o->max_rhi_iter < 1) return fail(ctx, NKS_E_INVALID, "max_rhi_iter must be >= 1");
     if (!(o->rhi_tol > 0.0)) return fail(ctx, NKS_E_INVALID, "rhi_tol must be > 0");
-    if (o->k_policy < NKS_POLICY_FIXED || o->k_policy > NKS_POLICY_DOUBLING ||
-        o->ell_policy < NKS_POLICY_FIXED || o->ell_policy > NKS_POLICY_DOUBLING)
-        return fail(ctx, NKS_E_UNSUPPORTED, "policy not available");
+    if (o->k_policy < NKS_POLICY_FIXED || o->k_policy > NKS_POLICY_LEARNED ||
+        o->ell_policy < NKS_POLICY_FIXED || o->ell_policy > NKS_POLICY_LEARNED)
+        return fail(ctx, NKS_E_INVALID, "unknown policy");
+    if ((o->k_policy == NKS_POLICY_LEARNED || o->ell_policy == NKS_POLICY_LEARNED) && !(ctx && ctx->net))
+        return fail(ctx, NKS_E_UNSUPPORTED, "learned policy needs a network (nks_policy_load)");
     if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
         return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
     return NKS_OK;
 }
 
-int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
+int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label = false) {
     if (njobs < 1 || !jobs) return fail(ctx, NKS_E_INVALID, "no jobs");
     std::vector<JobPlan> tmp;
     for (int i = 0; i < njobs; ++i) {
@@ -130,6 +136,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
         jp.k_policy = J.opts->k_policy;
         jp.ell_policy = J.opts->ell_policy;
         jp.tol = J.opts->tol;
+        jp.label = label;
         jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
         if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
             return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
@@ -161,15 +168,18 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P) {
         jp.off_status = off; off = align_up(off + sizeof(int) * ST_COUNT);
         jp.off_report = off; off = align_up(off + sizeof(double) * RP_COUNT);
         jp.off_omega = off; off = align_up(off + sizeof(double2) * jp.k);
-        jp.off_ckpt = off; off = align_up(off + (jp.k_policy != NKS_POLICY_FIXED ? sizeof(double2) * jp.k : 0));
-        jp.off_nest = off; off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided));
+        const bool ck = jp.k_policy != NKS_POLICY_FIXED || jp.label;
+        jp.off_ckpt = off; off = align_up(off + (ck ? sizeof(double2) * jp.k : 0));
+        jp.off_label = off; off = align_up(off + (jp.label ? sizeof(double) * LABEL_WORDS : 0));
+        jp.off_nest = off;
+        off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided) * (jp.label ? 1 + LABEL_NK : 1));
         jp.end = off;
     }
     P.total = off;
     return NKS_OK;
 }
 
-JobDesc make_desc(const JobPlan& jp, char* ws, const void* b, void* x) {
+JobDesc make_desc(const nks_ctx* ctx, const JobPlan& jp, char* ws, const void* b, void* x) {
     JobDesc d{};
     d.b = static_cast<const double2*>(b);
     d.x = static_cast<double2*>(x);
@@ -195,7 +205,11 @@ JobDesc make_desc(const JobPlan& jp, char* ws, const void* b, void* x) {
     d.k_policy = jp.k_policy;
     d.ell_policy = jp.ell_policy;
     d.tol = jp.tol;
-    d.ckpt = jp.k_policy != NKS_POLICY_FIXED ? reinterpret_cast<double2*>(ws + jp.off_ckpt) : nullptr;
+    d.ckpt = (jp.k_policy != NKS_POLICY_FIXED || jp.label) ? reinterpret_cast<double2*>(ws + jp.off_ckpt) : nullptr;
+    d.label = jp.label ? reinterpret_cast<double*>(ws + jp.off_label) : nullptr;
+    d.mu = jp.lat->mu;
+    d.V = jp.lat->g.V;
+    d.net = jp.learned() ? ctx->net : nullptr;
     return d;
 }
 
@@ -266,7 +280,7 @@ double bytes_lift(const OuterLaunch& L, const Plan& P, int start) {
     return per_site * L.g.V;
 }
 
-enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1 };
+enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1, PH_LABEL = 2 };
 
 // Enqueue the whole method for all jobs.  Events (if non-null) mark phase ends.
 int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s,
@@ -277,8 +291,12 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const int start = P.groups[gi].first;
-        bool kpol = false;
-        for (int i = start; i < start + L.njobs; ++i) kpol = kpol || P.jobs[i].k_policy != NKS_POLICY_FIXED;
+        bool kpol = false, learned = false, klearned = false;
+        for (int i = start; i < start + L.njobs; ++i) {
+            kpol = kpol || P.jobs[i].k_policy != NKS_POLICY_FIXED;
+            learned = learned || P.jobs[i].learned();
+            klearned = klearned || P.jobs[i].k_policy == NKS_POLICY_LEARNED;
+        }
         launch_pack(L, s);
         for (int j = 1; j <= L.kmax; ++j) {
             int r = prof_begin(ctx, NKS_K_STENCIL, ctx->prof ? bytes_S(L, P, start, j) : 0.0, s);
@@ -288,7 +306,10 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
                 r = prof_begin(ctx, NKS_K_RECUR, ctx->prof ? bytes_R(L, P, start, j) : 0.0, s);
                 launch_outer_R(L, j, s);
                 prof_end(ctx, r, s);
-                if (kpol && j % CKPT_DK == 0) launch_checkpoint(L.jobs, L.njobs, j, s);
+                if (learned && j == LEARN_K0) launch_predict(L.jobs, L.njobs, j, s);
+                // plain checkpoints every CKPT_DK; a learned k target is a multiple of LEARN_DK
+                if (kpol && (j % CKPT_DK == 0 || (klearned && j > LEARN_K0 && j % LEARN_DK == 0)))
+                    launch_checkpoint(L.jobs, L.njobs, j, s);
             }
         }
     }
@@ -296,6 +317,11 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
     if (phase == PH_OUTER_ONLY) return NKS_OK;
+    if (phase == PH_LABEL) {
+        launch_label(table, (int)descs.size(), s);
+        HIP_TRY(ctx, hipGetLastError());
+        return NKS_OK;
+    }
     {
         const long long c = ctx->prof_count[NKS_K_NESTED];
         ctx->prof_count[NKS_K_NESTED] = 0;   // the nested launch is always timed when profiling
@@ -397,6 +423,7 @@ void nks_destroy(nks_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->net) (void)hipFree(ctx->net);
     delete ctx;
 }
 
@@ -502,7 +529,7 @@ int nks_sign_apply_batch(nks_ctx* ctx, int njobs, const nks_job* jobs, void* ws,
     char* w = static_cast<char*>(ws);
     std::vector<JobDesc>& descs = ctx->descs;
     descs.clear();
-    for (const auto& jp : P.jobs) descs.push_back(make_desc(jp, w, jobs[jp.idx].b, jobs[jp.idx].x));
+    for (const auto& jp : P.jobs) descs.push_back(make_desc(ctx, jp, w, jobs[jp.idx].b, jobs[jp.idx].x));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool timed = stats != nullptr;
     rc = enqueue(ctx, P, descs, w, s, timed, PH_ALL);
@@ -530,7 +557,7 @@ int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opt
     if (rc) return rc;
     if (!ws || ws_bytes < P.total) return fail(ctx, NKS_E_NOMEM, "workspace too small");
     char* w = static_cast<char*>(ws);
-    std::vector<JobDesc> descs{make_desc(P.jobs[0], w, b, nullptr)};
+    std::vector<JobDesc> descs{make_desc(ctx, P.jobs[0], w, b, nullptr)};
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = enqueue(ctx, P, descs, w, s, false, PH_OUTER_ONLY);
     if (rc) return rc;
@@ -571,6 +598,8 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
     if (k < 1) return fail(ctx, NKS_E_INVALID, "k must be >= 1");
     int rc = validate_opts(ctx, opts);
     if (rc) return rc;
+    if (opts->ell_policy == NKS_POLICY_LEARNED || opts->k_policy != NKS_POLICY_FIXED)
+        return fail(ctx, NKS_E_UNSUPPORTED, "nks_nested_step takes FIXED k and a FIXED or DOUBLING ell policy");
     const int ell = even_up(opts->ell);
     if (ell >= k && k > NONNESTED_MAX) return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode limited to k <= 1024");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -667,6 +696,52 @@ int nks_mlp_adam_step(nks_ctx* ctx, float* params, const float* grad, float* m, 
     if (!ctx || !params || !grad || !m || !v || step < 1) return fail(ctx, NKS_E_INVALID, "bad nks_mlp_adam_step arguments");
     launch_mlp_adam(params, grad, m, v, step, lr, static_cast<hipStream_t>(stream));
     HIP_TRY(ctx, hipGetLastError());
+    return NKS_OK;
+}
+
+int nks_policy_load(nks_ctx* ctx, const float* blob, int nfloats) {
+    if (!ctx || !blob) return fail(ctx, NKS_E_INVALID, "NULL argument");
+    if (nfloats != NKS_POLICY_NFLOATS || sizeof(PolicyNet) != sizeof(float) * NKS_POLICY_NFLOATS)
+        return fail(ctx, NKS_E_INVALID, "policy blob must hold NKS_POLICY_NFLOATS floats");
+    for (int i = 0; i < nfloats; ++i)
+        if (!(blob[i] == blob[i]) || blob[i] > 1e30f || blob[i] < -1e30f)
+            return fail(ctx, NKS_E_INVALID, "policy blob holds a non-finite value");
+    PolicyNet h;
+    std::memcpy(&h, blob, sizeof(h));
+    for (int i = 0; i < NFEAT; ++i)
+        if (!(h.fstd[i] > 0.f)) return fail(ctx, NKS_E_INVALID, "feature scales must be > 0");
+    for (int i = 0; i < 2; ++i)
+        if (!(h.tstd[i] > 0.f)) return fail(ctx, NKS_E_INVALID, "target scales must be > 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (!ctx->net) HIP_TRY(ctx, hipMalloc(&ctx->net, sizeof(PolicyNet)));
+    HIP_TRY(ctx, hipDeviceSynchronize());   // no call in flight may read the old network
+    HIP_TRY(ctx, hipMemcpy(ctx->net, &h, sizeof(h), hipMemcpyHostToDevice));
+    return NKS_OK;
+}
+
+int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* labels_host) {
+    if (!ctx || !labels_host) return fail(ctx, NKS_E_INVALID, "NULL argument");
+    if (njobs < 1 || !jobs) return fail(ctx, NKS_E_INVALID, "no jobs");
+    for (int i = 0; i < njobs; ++i) {
+        if (!jobs[i].b || !jobs[i].opts) return fail(ctx, NKS_E_INVALID, "job b or opts is NULL");
+        if (jobs[i].opts->k_policy != NKS_POLICY_FIXED || jobs[i].opts->ell_policy != NKS_POLICY_FIXED)
+            return fail(ctx, NKS_E_INVALID, "label runs take FIXED policies (the outer loop runs to opts.k)");
+    }
+    Plan P;
+    int rc = make_plan(ctx, njobs, jobs, P, true);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    char* w = nullptr;
+    HIP_TRY(ctx, hipMalloc(&w, P.total));
+    std::unique_ptr<char, decltype(&hipFree)> guard(w, &hipFree);
+    std::vector<JobDesc> descs;
+    for (const auto& jp : P.jobs) descs.push_back(make_desc(ctx, jp, w, jobs[jp.idx].b, nullptr));
+    rc = enqueue(ctx, P, descs, w, nullptr, false, PH_LABEL);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    for (const auto& jp : P.jobs)
+        HIP_TRY(ctx, hipMemcpy(labels_host + (size_t)jp.idx * LABEL_WORDS, w + jp.off_label,
+                               sizeof(double) * LABEL_WORDS, hipMemcpyDeviceToHost));
     return NKS_OK;
 }
 

@@ -794,26 +794,38 @@ struct NestResult {
     double p = 0.0, zmin = 0.0, zmax = 0.0, inner_delta = 0.0;
 };
 
-// Steps 3-5 on H_k (k = kk) with the job's ell policy; the result c is left in P.cc.
+// H_k (k = kk) from the job's scalars into the nest area
 template <typename T>
-__device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk, const Smem& sm) {
-    const int tid = threadIdx.x;
-    double2* sc = J.sc;
+__device__ void load_H(const JobDesc& J, const NestPtrs& P, int kk) {
+    const double2* sc = J.sc;
     const size_t st = J.scstride;
     T* d = (T*)P.d;
     T* sub = (T*)P.sub;
     T* sup = (T*)P.sup;
-    for (int i = tid; i < kk; i += NT) {
+    for (int i = threadIdx.x; i < kk; i += NT) {
         d[i] = s_from<T>(sc[SC_ALPHA * st + i + 1]);
         if (i + 1 < kk) { sub[i] = s_from<T>(sc[SC_BETA * st + i + 1]); sup[i] = s_from<T>(sc[SC_GAMMA * st + i + 1]); }
     }
     __syncthreads();
+}
+
+// Steps 3-5 on H_k (k = kk); the result c is left in P.cc.  ell-doubling runs
+// when the job's ell policy asks for it or force_doubling; it starts at
+// ell_start (0: ELL0), stops at tol/10 (tol < 0: the job's), and records each
+// doubling's change in trace[0..ntrace).
+template <typename T>
+__device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk, const Smem& sm, int ell_start = 0,
+                                    double tol = -1.0, bool force_doubling = false, double* trace = nullptr,
+                                    int ntrace = 0) {
+    const int tid = threadIdx.x;
+    load_H<T>(J, P, kk);
     T* cc = (T*)P.cc;
     T* cp = (T*)P.cp;
     NestResult res;
+    if (tol < 0.0) tol = J.tol;
     const int cap = min(J.lcap, kk);   // largest inner size allowed
-    const bool doubling = J.ell_policy != NKS_POLICY_FIXED;
-    const int ell0 = doubling ? ELL0 : J.ell;
+    const bool doubling = force_doubling || J.ell_policy != NKS_POLICY_FIXED;
+    const int ell0 = doubling ? (ell_start > 0 ? ell_start : ELL0) : J.ell;
     if (ell0 >= kk || (doubling && ell0 >= cap && cap >= kk)) {
         res.rhi = nonnested_coeffs<T>(J, P, kk, cc, sm);
         res.ell = 0;
@@ -837,12 +849,14 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
         inner_extend<T>(P, kk, p, ell, in, sm);
         res.rhi = inner_coeffs<T>(J, P, kk, in.i, cp, sm);
         res.ell = in.i;
+        int step = 0;
         while (true) {
             const int ell2 = 2 * ell;
             if (ell2 >= cap && cap >= kk) {          // the inner space would be the whole of H_k
                 res.rhi = nonnested_coeffs<T>(J, P, kk, cc, sm);
                 res.inner_delta = rel_change<T>(cc, cp, kk, sm);
                 res.ell = 0;
+                if (trace && step < ntrace && tid == 0) trace[step] = res.inner_delta;
                 break;
             }
             const int target = min(ell2, cap);
@@ -850,7 +864,9 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
             res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
             res.ell = in.i;
             res.inner_delta = rel_change<T>(cc, cp, kk, sm);
-            if (res.inner_delta <= J.tol / 10 || target >= cap || in.ended) break;
+            if (trace && step < ntrace && tid == 0) trace[step] = res.inner_delta;
+            ++step;
+            if (res.inner_delta <= tol / 10 || target >= cap || in.ended) break;
             for (int i = tid; i < kk; i += NT) cp[i] = cc[i];
             __syncthreads();
             ell = ell2;
@@ -860,56 +876,100 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     return res;
 }
 
-enum NestMode { NEST_FINAL = 0, NEST_CHECKPOINT = 1 };
-
+// weighted change |c - [c_prev; 0]|_w / |c|_w with ||d||_w^2 = sum |d_i|^2 ||v_{i+1}||^2
 template <typename T>
-__device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm) {
-    const int tid = threadIdx.x;
+__device__ double weighted_change(const JobDesc& J, const T* c, int kk, const double2* prev, int kprev,
+                                  const Smem& sm) {
+    const double2* VN = J.sc + SC_VN * J.scstride;
+    double dn = 0.0, cn = 0.0;
+    for (int i = threadIdx.x; i < kk; i += NT) {
+        const double w2 = cabs2(VN[i + 1]);
+        const double2 ci = s_d2(c[i]);
+        const double2 di = (i < kprev) ? csub(ci, prev[i]) : ci;
+        dn += cabs2(di) * w2;
+        cn += cabs2(ci) * w2;
+    }
+    const double2 r = block_sum<NT>(mk(dn, cn), sm.red);
+    return sqrt(r.x) / sqrt(r.y);
+}
+
+// ---------------------------------------------------------------- learned policy
+// Features of the probe Ritz matrix H_{k0} (all threads get them).
+template <typename T>
+__device__ void job_features(const JobDesc& J, const NestPtrs& P, int k0, const Smem& sm, double* f) {
+    double zmin, zmax, zmin2, zmax2;
+    load_H<T>(J, P, k0);
+    estimate_extremes<T>(J, P, k0, sm, zmin, zmax);
+    const int kh = max(2, k0 / 2);
+    load_H<T>(J, P, kh);
+    estimate_extremes<T>(J, P, kh, sm, zmin2, zmax2);
+    const double2* sc = J.sc;
     const size_t st = J.scstride;
-    const double2* SV = J.sc + SC_SV * st;
-    const double2* VN = J.sc + SC_VN * st;
-    const bool kpol = J.k_policy != NKS_POLICY_FIXED;
-    int kk;
-    if (mode == NEST_CHECKPOINT) {
-        if (!kpol || J.status[ST_DONE] || j >= J.k) return;
-        kk = j;
-    } else {
-        kk = J.status[ST_KUSED];
-        if (kk == 0) return;                              // zero source; lift writes zeros
-        if (J.status[ST_CKPT_DONE]) {                     // a checkpoint already accepted H_kk
-            return;
-        }
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < k0; i += NT) {
+        sa += cabs(sc[SC_ALPHA * st + i + 1]);
+        if (i + 1 < k0) sb += sqrt(cabs(cmul(sc[SC_BETA * st + i + 1], sc[SC_GAMMA * st + i + 1])));
     }
-    NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
-    NestResult res = nested_coeffs<T>(J, P, kk, sm);
-    const T* cc = (const T*)P.cc;
-    double outer_delta = -1.0;
-    if (kpol && J.status[ST_NCKPT] > 0 && res.status == NKS_OK) {
-        // change against the previous checkpoint, weighted by the basis norms
-        const int kprev = J.status[ST_KCKPT];
-        double dn = 0.0, cn = 0.0;
-        for (int i = tid; i < kk; i += NT) {
-            const double w2 = cabs2(VN[i + 1]);
-            const double2 ci = s_d2(cc[i]);
-            const double2 di = (i < kprev) ? csub(ci, J.ckpt[i]) : ci;
-            dn += cabs2(di) * w2;
-            cn += cabs2(ci) * w2;
-        }
-        const double2 r = block_sum<NT>(mk(dn, cn), sm.red);
-        outer_delta = sqrt(r.x) / sqrt(r.y);
+    const double2 r = block_sum<NT>(mk(sa, sb), sm.red);
+    for (int i = 0; i < NFEAT; ++i) f[i] = 0.0;
+    f[0] = 1.0;
+    f[1] = log10(zmin);
+    f[2] = log10(zmax);
+    f[3] = log10(zmin2);
+    f[4] = log10(zmax / zmin);
+    f[5] = J.mu;
+    f[6] = log10(J.tol);
+    f[7] = J.two_sided ? 1.0 : 0.0;
+    f[8] = log10((double)J.V);
+    f[9] = r.x / k0;
+    f[10] = r.y / max(k0 - 1, 1);
+}
+
+__device__ inline float bf16r(float x) {   // round to the nearest bfloat16 (ties to even)
+    unsigned int u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ inline float silu_f(float z) { return z / (1.0f + expf(-z)); }
+
+// Network inference for one feature vector (same rounding as the training
+// kernels: bf16 weights and layer inputs, float32 accumulation).  Result in out[2].
+__device__ void net_forward(const PolicyNet* net, const double* f, float* out) {
+    __shared__ float x[NFEAT], h1[64], h2[64];
+    const int tid = threadIdx.x;
+    const float* P = net->params;
+    if (tid < NFEAT) x[tid] = bf16r(((float)f[tid] - net->fmean[tid]) / net->fstd[tid]);
+    __syncthreads();
+    if (tid < 64) {
+        float z = P[16 * 64 + tid];
+        for (int i = 0; i < 16; ++i) z += x[i] * bf16r(P[i * 64 + tid]);
+        h1[tid] = bf16r(silu_f(z));
     }
-    const bool accept = mode == NEST_CHECKPOINT && outer_delta >= 0.0 && outer_delta <= J.tol / 4;
-    if (mode == NEST_CHECKPOINT && !accept) {
-        for (int i = tid; i < kk; i += NT) J.ckpt[i] = s_d2(cc[i]);
-        __syncthreads();
-        if (tid == 0) {
-            J.status[ST_KCKPT] = kk;
-            J.status[ST_NCKPT] += 1;
-            J.report[RP_OUTER_DELTA] = outer_delta;
-        }
-        return;
+    __syncthreads();
+    if (tid < 64) {
+        const float* W2 = P + 16 * 64 + 64;
+        float z = W2[64 * 64 + tid];
+        for (int i = 0; i < 64; ++i) z += h1[i] * bf16r(W2[i * 64 + tid]);
+        h2[tid] = bf16r(silu_f(z));
     }
-    // final result (or an accepted checkpoint): lift weights omega_j = |b| c_j sv_j
+    __syncthreads();
+    if (tid < 2) {
+        const float* W3 = P + 16 * 64 + 64 + 64 * 64 + 64;
+        float z = W3[64 * 2 + tid];
+        for (int i = 0; i < 64; ++i) z += h2[i] * bf16r(W3[i * 2 + tid]);
+        out[tid] = z * net->tstd[tid] + net->tmean[tid];
+    }
+    __syncthreads();
+}
+
+enum NestMode { NEST_FINAL = 0, NEST_CHECKPOINT = 1, NEST_PREDICT = 2, NEST_LABEL = 3 };
+
+// Final result (or an accepted checkpoint): lift weights and the job report.
+template <typename T>
+__device__ void write_result(const JobDesc& J, const T* cc, int kk, const NestResult& res, double outer_delta,
+                             bool accept, bool kpol) {
+    const int tid = threadIdx.x;
+    const double2* SV = J.sc + SC_SV * J.scstride;
     const double bnorm = J.report[RP_BNORM];
     for (int q = tid; q < kk; q += NT) J.omega[q] = cscale(cmul(s_d2(cc[q]), SV[q + 1]), bnorm);
     if (tid == 0) {
@@ -921,9 +981,10 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm) {
         int status = J.status[ST_STATUS];
         if (status == NKS_OK && res.status != NKS_OK) status = res.status;
         if (status == NKS_OK && res.rhi < 0) status = NKS_E_NOCONV;
-        if (status == NKS_OK && J.ell_policy != NKS_POLICY_FIXED && res.inner_delta > J.tol / 10)
+        // (a final non-nested step, ell = 0, is exact in ell and never counts)
+        if (status == NKS_OK && J.ell_policy != NKS_POLICY_FIXED && res.ell != 0 && res.inner_delta > J.tol / 10)
             status = NKS_E_NOCONV;
-        // k policy that ran to its cap without meeting tol (a lucky breakdown is exact)
+        // a k policy that ran to its cap without meeting tol (a lucky breakdown is exact)
         if (status == NKS_OK && kpol && !accept && J.status[ST_DONE] == 0 &&
             (outer_delta < 0.0 || outer_delta > J.tol / 4))
             status = NKS_E_NOCONV;
@@ -936,9 +997,164 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm) {
         J.report[RP_INNER_DELTA] = res.inner_delta;
         if (outer_delta >= 0.0) J.report[RP_OUTER_DELTA] = outer_delta;
     }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void store_checkpoint(const JobDesc& J, const T* cc, int kk, double outer_delta) {
+    for (int i = threadIdx.x; i < kk; i += NT) J.ckpt[i] = s_d2(cc[i]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        J.status[ST_KCKPT] = kk;
+        J.status[ST_NCKPT] += 1;
+        if (outer_delta >= 0.0) J.report[RP_OUTER_DELTA] = outer_delta;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm, float* net_out) {
+    const int tid = threadIdx.x;
+    const bool learned = J.k_policy == NKS_POLICY_LEARNED;
+    const bool kpol = J.k_policy != NKS_POLICY_FIXED;
+    NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
+    const T* cc = (const T*)P.cc;
+    const int ell_start = J.ell_policy == NKS_POLICY_LEARNED ? J.status[ST_ELLSTART] : 0;
+
+    if (mode == NEST_PREDICT) {
+        // learned policy: features of H_{k0} -> network -> k*, ell*
+        if (!J.net || J.status[ST_DONE] || j >= J.k) return;
+        __shared__ double f[NFEAT];
+        double fl[NFEAT];
+        job_features<T>(J, P, j, sm, fl);
+        if (tid < NFEAT) f[tid] = fl[tid];
+        __syncthreads();
+        net_forward(J.net, f, net_out);
+        if (tid == 0) {
+            const double ks = pow(10.0, (double)net_out[0]);
+            const double ls = pow(10.0, (double)net_out[1]);
+            int kt = (int)ceil(ks / LEARN_DK) * LEARN_DK;
+            kt = max(kt, j + LEARN_DK);
+            if (learned && kt < J.k) J.status[ST_KTARGET] = kt;
+            // nearest power of two (geometric), at least 8
+            int es = 8;
+            while (es * 1.4142135623730951 < ls && es < J.lcap) es *= 2;
+            J.status[ST_ELLSTART] = es;
+        }
+        __syncthreads();
+        return;
+    }
+
+    if (mode == NEST_LABEL) {
+        // features of H_{k0} and the reference c_ref = c(k_used) (label_kernel does the rest)
+        if (!J.label) return;
+        const int kused = J.status[ST_KUSED];
+        double* L = J.label;
+        for (int i = tid; i < LABEL_WORDS; i += NT) L[i] = nan("");
+        __syncthreads();
+        if (kused < LEARN_K0 + LABEL_DK) return;
+        double fl[NFEAT];
+        job_features<T>(J, P, LEARN_K0, sm, fl);
+        if (tid < NFEAT) L[tid] = fl[tid];
+        __syncthreads();
+        nested_coeffs<T>(J, P, kused, sm, 0, LABEL_TOL, true);
+        for (int i = tid; i < kused; i += NT) J.ckpt[i] = s_d2(cc[i]);
+        __syncthreads();
+        return;
+    }
+
+    if (mode == NEST_CHECKPOINT) {
+        if (!kpol || J.status[ST_DONE] || j >= J.k) return;
+        if (learned && !J.status[ST_FALLBACK] && J.status[ST_KTARGET] > 0) {
+            if (j != J.status[ST_KTARGET]) return;
+            // verify k* against k* - LEARN_VERIFY_DK
+            const int kv = j - LEARN_VERIFY_DK;
+            NestResult r0 = nested_coeffs<T>(J, P, kv, sm, ell_start);
+            store_checkpoint<T>(J, cc, kv, -1.0);
+            NestResult res = nested_coeffs<T>(J, P, j, sm, ell_start);
+            const double delta = weighted_change<T>(J, cc, j, J.ckpt, kv, sm);
+            (void)r0;
+            if (delta <= J.tol / 4 && res.status == NKS_OK) {
+                write_result<T>(J, cc, j, res, delta, true, true);
+            } else {
+                // fall back to the plain checkpoints from here on
+                store_checkpoint<T>(J, cc, j, delta);
+                if (tid == 0) {
+                    J.status[ST_FALLBACK] = 1;
+                    J.status[ST_KTARGET] = 0;
+                }
+                __syncthreads();
+            }
+            return;
+        }
+        if (j % CKPT_DK != 0) return;
+        NestResult res = nested_coeffs<T>(J, P, j, sm, ell_start);
+        double outer_delta = -1.0;
+        if (J.status[ST_NCKPT] > 0 && res.status == NKS_OK)
+            outer_delta = weighted_change<T>(J, cc, j, J.ckpt, J.status[ST_KCKPT], sm);
+        if (outer_delta >= 0.0 && outer_delta <= J.tol / 4) write_result<T>(J, cc, j, res, outer_delta, true, true);
+        else store_checkpoint<T>(J, cc, j, outer_delta);
+        return;
+    }
+
+    // NEST_FINAL
+    const int kk = J.status[ST_KUSED];
+    if (kk == 0) return;                              // zero source; lift writes zeros
+    if (J.status[ST_CKPT_DONE]) return;               // a checkpoint already accepted H_kk
+    NestResult res = nested_coeffs<T>(J, P, kk, sm, ell_start);
+    double outer_delta = -1.0;
+    if (kpol && J.status[ST_NCKPT] > 0 && res.status == NKS_OK)
+        outer_delta = weighted_change<T>(J, cc, kk, J.ckpt, J.status[ST_KCKPT], sm);
+    write_result<T>(J, cc, kk, res, outer_delta, false, kpol);
 }
 
 __global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int j) {
+    __shared__ double2 red[NT / 64];
+    __shared__ double redd[NT / 64];
+    __shared__ int redi[NT / 64];
+    __shared__ Aff2<double2> scan_lds[NT];
+    __shared__ float net_out[2];
+    Smem sm;
+    sm.red = red;
+    sm.redd = redd;
+    sm.redi = redi;
+    sm.scan = scan_lds;
+    const JobDesc& J = jobs[blockIdx.x];
+    if (J.two_sided) nested_job<double2>(J, mode, j, sm, net_out);
+    else nested_job<double>(J, mode, j, sm, net_out);
+}
+
+// Label run, one workgroup per (job, k_i): c(k_i) with the ell doubling traced,
+// and its weighted error against c_ref.  Each k_i has its own nested scratch.
+template <typename T>
+__device__ void label_point(const JobDesc& J, int i, const Smem& sm) {
+    const int tid = threadIdx.x;
+    const int kused = J.status[ST_KUSED];
+    const int ki = LABEL_DK * (i + 1);
+    if (!J.label || kused < LEARN_K0 + LABEL_DK || ki > kused) return;
+    NestPtrs P = nest_ptrs(J.nest + (size_t)(i + 1) * J.nest_cap, J.k, J.lcap);
+    const T* cc = (const T*)P.cc;
+    __shared__ double trace[LABEL_NELL];
+    if (tid < LABEL_NELL) trace[tid] = nan("");
+    __syncthreads();
+    nested_coeffs<T>(J, P, ki, sm, 0, LABEL_TOL, true, trace, LABEL_NELL);
+    const double2* VN = J.sc + SC_VN * J.scstride;
+    double dn = 0.0, rn = 0.0;
+    for (int q = tid; q < kused; q += NT) {
+        const double w2 = cabs2(VN[q + 1]);
+        const double2 c = (q < ki) ? s_d2(cc[q]) : mk(0.0, 0.0);
+        dn += cabs2(csub(c, J.ckpt[q])) * w2;
+        rn += cabs2(J.ckpt[q]) * w2;
+    }
+    const double2 r = block_sum<NT>(mk(dn, rn), sm.red);
+    if (tid == 0) {
+        double* L = J.label;
+        L[NFEAT + i] = sqrt(r.x) / sqrt(r.y);
+        for (int e = 0; e < LABEL_NELL; ++e) L[NFEAT + LABEL_NK + i * LABEL_NELL + e] = trace[e];
+    }
+}
+
+__global__ __launch_bounds__(NT) void label_kernel(JobDesc* jobs) {
     __shared__ double2 red[NT / 64];
     __shared__ double redd[NT / 64];
     __shared__ int redi[NT / 64];
@@ -949,8 +1165,8 @@ __global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int
     sm.redi = redi;
     sm.scan = scan_lds;
     const JobDesc& J = jobs[blockIdx.x];
-    if (J.two_sided) nested_job<double2>(J, mode, j, sm);
-    else nested_job<double>(J, mode, j, sm);
+    if (J.two_sided) label_point<double2>(J, blockIdx.y, sm);
+    else label_point<double>(J, blockIdx.y, sm);
 }
 
 // H(k,k) = alpha_k from the partial sums of the last stencil pass (the
@@ -984,6 +1200,15 @@ void launch_nested(JobDesc* jobs, int njobs, hipStream_t s) {
 
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s) {
     hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_CHECKPOINT, j);
+}
+
+void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s) {
+    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_PREDICT, j);
+}
+
+void launch_label(JobDesc* jobs, int njobs, hipStream_t s) {
+    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_LABEL, 0);
+    hipLaunchKernelGGL(label_kernel, dim3(njobs, LABEL_NK), dim3(NT), 0, s, jobs);
 }
 
 }  // namespace nks

@@ -92,6 +92,9 @@ enum StatusWord {
     ST_CKPT_DONE = 6,   // a k-checkpoint accepted the result (omega already written)
     ST_NCKPT = 7,       // k-checkpoints stored so far
     ST_KCKPT = 8,       // size of the stored checkpoint coefficients
+    ST_KTARGET = 9,     // learned policy: predicted outer size (0 = none)
+    ST_ELLSTART = 10,   // learned policy: first inner size of the doubling (0 = default)
+    ST_FALLBACK = 11,   // learned policy: prediction rejected, plain checkpoints took over
     ST_COUNT = 16
 };
 
@@ -136,9 +139,36 @@ struct JobDesc {
     int ell_policy;
     double tol;         // target relative accuracy of the policies
     double2* ckpt;      // coefficients of the last k-checkpoint (kcap)
+    double mu;          // chemical potential of the job's lattice
+    int V;              // lattice volume
+    const struct PolicyNet* net;   // learned policy (device), or null
+    double* label;      // label mode output (LABEL_WORDS doubles), or null
 };
 
-constexpr int CKPT_DK = 100;   // outer iterations between k-checkpoints
+constexpr int CKPT_DK = 100;     // outer iterations between plain k-checkpoints
+constexpr int LEARN_K0 = 100;    // probe length of the learned policy (features of H_{k0})
+constexpr int LEARN_DK = 20;     // granularity of the learned k and of its verification
+constexpr int LEARN_VERIFY_DK = 40;   // k* is verified against k* - 40
+
+// Learned policy: network parameters and normalisation, resident on the device.
+constexpr int NFEAT = 16;
+struct PolicyNet {
+    float params[5378];
+    float fmean[NFEAT], fstd[NFEAT];   // feature normalisation
+    float tmean[2], tstd[2];           // targets: log10 k*, log10 ell*
+};
+
+// Label mode output per job (doubles): features of H_{k0}, the weighted error of
+// the nested result at k = LABEL_DK * (i + 1) against the job's final result,
+// and the ell-doubling changes (16 -> 32, 32 -> 64, 64 -> 128, 128 -> 256) at each k.
+// A label job owns 1 + LABEL_NK nested scratch areas of nest_cap words each.
+constexpr int LABEL_NK = 60, LABEL_NELL = 4, LABEL_DK = 20;
+constexpr double LABEL_TOL = 1e-13;   // ell doubling of the label runs stops at a change <= LABEL_TOL / 10
+constexpr int LABEL_WORDS = NFEAT + LABEL_NK + LABEL_NK * LABEL_NELL;
+static_assert(LABEL_WORDS == NKS_LABEL_WORDS && NFEAT == NKS_POLICY_NFEAT && LEARN_K0 == NKS_LEARN_K0 &&
+                  LABEL_NK == NKS_LABEL_NK && LABEL_NELL == NKS_LABEL_NELL && LABEL_DK == NKS_LABEL_DK,
+              "label layout must match the public header");
+static_assert(sizeof(PolicyNet) == sizeof(float) * NKS_POLICY_NFLOATS, "PolicyNet layout");
 
 // ----------------------------------------------------------------- reductions
 __device__ inline double2 shfl_xor_d2(double2 v, int m) {
@@ -206,6 +236,8 @@ constexpr int NEST_NT = 256;
 void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s);
 void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // after R_j
+void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s);      // after R_{k0}
+void launch_label(JobDesc* jobs, int njobs, hipStream_t s);               // after the outer loop
 size_t nest_words(int k, int ell, int two_sided);
 
 // mlp.hip
