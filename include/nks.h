@@ -83,7 +83,8 @@ typedef struct nks_opts {
     size_t size;          /* sizeof(nks_opts), for versioning */
     int k;                /* outer Krylov size (the largest k under the k policy); rounded up to even */
     int ell;              /* inner Krylov size (the largest under the ell policy); rounded up to
-                             even; ell >= k -> non-nested RHi on H_k */
+                             even; ell >= k -> non-nested RHi on H_k.  The dense RHi matrix
+                             (ell, or k when non-nested) is limited to 1024 (NKS_E_UNSUPPORTED) */
     double tol;           /* target relative accuracy for the policies */
     int precision;        /* enum nks_precision */
     double p;             /* preconditioner factor of Eq. precond; <= 0 -> p_opt of Eq. popt
@@ -213,8 +214,8 @@ int nks_mlp_adam_step(nks_ctx* ctx, float* params, const float* grad, float* m, 
  * NKS_LABEL_DK (at least k0 + 20, else no target) and accepts H_{k_t}
  * if the weighted coefficient change against H_{k_t - 40} is <= tol/4;
  * otherwise it continues with the checkpoints of NKS_POLICY_DOUBLING.  The
- * ell policy starts its doubling at the power of two >= ell* (>= 8), with
- * the DOUBLING acceptance rule.  A learned policy on a job with k <= k0 + 20
+ * ell policy starts its doubling at the largest power of two <= 1.05 ell*
+ * (>= 8), with the DOUBLING acceptance rule.  A learned policy on a job with k <= k0 + 20
  * behaves as DOUBLING.
  *
  * nks_policy_load copies a network to the device, for every later call

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "FP64", "MIXED", "POLICY_FIXED", "POLICY_DOUBLING", "POLICY_LEARNED",
     "NKSError", "lib", "Context", "Lattice", "apply_op", "sign_apply", "sign_apply_batch",
-    "outer_basis", "nested_step", "workspace_size", "LIB_PATH", "policy_load", "policy_label",
+    "outer_basis", "nested_step", "workspace_size", "LIB_PATH", "policy_load", "policy_label", "load_policy",
     "mlp_forward", "mlp_backward", "mlp_adam_step",
 ]
 
@@ -370,6 +370,16 @@ def policy_load(ctx: Context, blob):
     parameters, feature mean/scale, target mean/scale) for later calls."""
     blob = np.ascontiguousarray(blob, dtype=np.float32).ravel()
     ctx.check(lib().nks_policy_load(ctx.h, blob.ctypes.data, int(blob.size)))
+
+
+def load_policy(ctx: Context, path: str | None = None) -> dict:
+    """Load the trained network shipped with the package (or the file at
+    path, written by ``python -m paper_0912_4457_amd.policy``); returns its
+    training metadata."""
+    from . import policy as _p
+    blob, meta = _p.load(path or _p.DEFAULT_PATH)
+    policy_load(ctx, blob)
+    return meta
 
 
 def policy_label(jobs):

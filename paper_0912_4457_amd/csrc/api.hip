@@ -59,7 +59,7 @@ int fail(nks_ctx* ctx, int code, const std::string& msg) {
 
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-constexpr int NONNESTED_MAX = 1024;   // dense k x k RHi limit of the non-nested mode
+constexpr int NONNESTED_MAX = RHI_MAX;   // dense k x k RHi limit of the non-nested mode
 
 __global__ void links_to_soa(const double2* __restrict__ in, double2* __restrict__ o64, float2* __restrict__ o32,
                              int V) {
@@ -140,6 +140,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
         if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
             return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
+        if (jp.lcap > RHI_MAX) return fail(ctx, NKS_E_UNSUPPORTED, "ell is limited to 1024");
         jp.nblocks = (J.lat->g.V + OUTER_NT - 1) / OUTER_NT;
         tmp.push_back(jp);
     }
@@ -602,6 +603,7 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
         return fail(ctx, NKS_E_UNSUPPORTED, "nks_nested_step takes FIXED k and a FIXED or DOUBLING ell policy");
     const int ell = even_up(opts->ell);
     if (ell >= k && k > NONNESTED_MAX) return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode limited to k <= 1024");
+    if (ell < k && ell > RHI_MAX) return fail(ctx, NKS_E_UNSUPPORTED, "ell is limited to 1024");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     // a one-job layout: descriptor, scalars, status, report, omega, nest
     const size_t stride = (size_t)k + 2;

@@ -403,46 +403,48 @@ __device__ double find_eig(const double2* d, const double2* sub, int k, int m, d
 
 // Dense in-place inversion of the n x n row-major matrix B (Gauss-Jordan,
 // partial pivoting).  Returns false if a pivot is exactly zero.
+// In-place Gauss-Jordan inversion with partial pivoting and implicit row
+// interchanges (the pivot rows are recorded, not moved).  After the sweep
+// B[perm[k]][pinv[m]] = (A^{-1})[k][m], with perm[k] the pivot row of column
+// k (global, n ints) and pinv its inverse (LDS, n ints).  fcol (LDS, n
+// entries) holds the pivot column, prow (n entries) the scaled pivot row.
+// Threads own columns, so row accesses are coalesced.  Returns false on a
+// zero pivot.  Used when the blocked form's panel does not fit in LDS.
 template <typename T>
-__device__ bool gj_invert(T* B, int n, T* prow, T* fcol, int* perm, double* ldsd, int* ldsi) {
+__device__ bool gj_invert_unblocked(T* __restrict__ B, int n, T* __restrict__ prow, int* __restrict__ perm,
+                                    T* __restrict__ fcol, int* __restrict__ pinv, double* ldsd, int* ldsi) {
+    const int tid = threadIdx.x;
+    const int nc = n < NT ? n : NT;          // columns per pass
+    const int groups = NT / nc;              // threads per column
+    const int g = tid / nc, jc = tid - (tid / nc) * nc;
     bool ok = true;
+    for (int i = tid; i < n; i += NT) pinv[i] = -1;
+    __syncthreads();
     for (int kk = 0; kk < n; ++kk) {
         double best = -1.0;
         int bidx = n;
-        for (int i = kk + threadIdx.x; i < n; i += NT) {
-            const double a = s_abs(B[(size_t)i * n + kk]);
+        for (int i = tid; i < n; i += NT) {
+            const T v = B[(size_t)i * n + kk];
+            fcol[i] = v;
+            const double a = pinv[i] < 0 ? s_abs(v) : -1.0;
             if (a > best) { best = a; bidx = i; }
         }
-        const int p = block_argmax(best, bidx, ldsd, ldsi);
-        if (threadIdx.x == 0) perm[kk] = p;
-        if (p != kk) {
-            for (int j = threadIdx.x; j < n; j += NT) {
-                const T t = B[(size_t)kk * n + j];
-                B[(size_t)kk * n + j] = B[(size_t)p * n + j];
-                B[(size_t)p * n + j] = t;
-            }
-        }
-        __syncthreads();
-        const T piv = B[(size_t)kk * n + kk];
+        const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
+        const T piv = fcol[p];
         if (s_abs1(piv) == 0.0) ok = false;
         const T pivinv = s_div(s_one<T>(), piv);
-        for (int j = threadIdx.x; j < n; j += NT) prow[j] = (j == kk) ? pivinv : s_mul(B[(size_t)kk * n + j], pivinv);
-        for (int i = threadIdx.x; i < n; i += NT) fcol[i] = (i == kk) ? s_zero<T>() : B[(size_t)i * n + kk];
+        for (int j = tid; j < n; j += NT) prow[j] = (j == kk) ? pivinv : s_mul(B[(size_t)p * n + j], pivinv);
         __syncthreads();
-        for (int e = threadIdx.x; e < n * n; e += NT) {
-            const int i = e / n, j = e - i * n;
-            if (i == kk) B[e] = prow[j];
-            else B[e] = s_sub((j == kk) ? s_zero<T>() : B[e], s_mul(fcol[i], prow[j]));
-        }
-        __syncthreads();
-    }
-    for (int kk = n - 1; kk >= 0; --kk) {
-        const int p = perm[kk];
-        if (p != kk) {
-            for (int i = threadIdx.x; i < n; i += NT) {
-                const T t = B[(size_t)i * n + kk];
-                B[(size_t)i * n + kk] = B[(size_t)i * n + p];
-                B[(size_t)i * n + p] = t;
+        if (tid == 0) { perm[kk] = p; pinv[p] = kk; }
+        if (g < groups) {
+            for (int j = jc; j < n; j += nc) {
+                const T pj = prow[j];
+                T* col = B + j;
+                for (int i = g; i < n; i += groups) {
+                    T* e = col + (size_t)i * n;
+                    if (i == p) *e = pj;
+                    else *e = s_sub((j == kk) ? s_zero<T>() : *e, s_mul(fcol[i], pj));
+                }
             }
         }
         __syncthreads();
@@ -450,25 +452,170 @@ __device__ bool gj_invert(T* B, int n, T* prow, T* fcol, int* perm, double* ldsd
     return ok;
 }
 
-// Roberts-Higham on the dense n x n matrix S (row-major); B is scratch.
-// Returns iterations (negative if not converged).
+// Blocked form of the same sweep.  Columns are taken NB at a time: the panel
+// B[:, k0:k0+nb] is eliminated in LDS (W), then the rest of B gets the
+// panel's combined effect in one pass,
+//   B[i][j] <- (i a pivot row of the panel ? 0 : B[i][j]) + sum_s W[i][s] R[s][j],
+// where R[s] is pivot row perm[k0+s] before the pass.  Each element of B is
+// read and written once per panel instead of once per column.
+constexpr int GJ_NB = 8;                 // widest panel
+constexpr int GJ_PANEL_BYTES = 32768;
+constexpr int GJ_CH = 8;                 // rows per prefetched chunk
+
+// Column j, rows i0, i0 + step, ... : the rank-nb update with the next chunk
+// of B loaded before the current one is stored.
+template <typename T, int NB>
+__device__ inline void panel_update_column(T* __restrict__ B, int n, int j, int i0, int step, int k0, int nb,
+                                           const T* __restrict__ W, const int* __restrict__ pinv, const T* R) {
+    T* col = B + j;
+    T cur[GJ_CH];
+#pragma unroll
+    for (int r = 0; r < GJ_CH; ++r) {
+        const int i = i0 + r * step;
+        cur[r] = i < n ? col[(size_t)i * n] : s_zero<T>();
+    }
+    for (int base = i0; base < n; base += GJ_CH * step) {
+        T nxt[GJ_CH];
+        const int nb0 = base + GJ_CH * step;
+#pragma unroll
+        for (int r = 0; r < GJ_CH; ++r) {
+            const int i = nb0 + r * step;
+            nxt[r] = i < n ? col[(size_t)i * n] : s_zero<T>();
+        }
+#pragma unroll
+        for (int r = 0; r < GJ_CH; ++r) {
+            const int i = base + r * step;
+            if (i < n) {
+                const int q = pinv[i];
+                T acc = (q >= k0 && q < k0 + nb) ? s_zero<T>() : cur[r];
+                const T* w = W + i * NB;
+#pragma unroll
+                for (int s2 = 0; s2 < NB; ++s2) acc = s_add(acc, s_mul(w[s2], R[s2]));
+                col[(size_t)i * n] = acc;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < GJ_CH; ++r) cur[r] = nxt[r];
+    }
+}
+
+template <typename T, int NB>
+__device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ perm, T* __restrict__ fcol,
+                                  int* __restrict__ pinv, T* __restrict__ W, double* ldsd, int* ldsi) {
+    const int tid = threadIdx.x;
+    T* pr = fcol - GJ_NB;                    // scaled pivot row of the panel (kept just before fcol)
+    bool ok = true;
+    for (int i = tid; i < n; i += NT) pinv[i] = -1;
+    __syncthreads();
+    const int nc = n < NT ? n : NT;
+    const int groups = NT / nc;
+    const int g = tid / nc, jc = tid - (tid / nc) * nc;
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nb = min(NB, n - k0);
+        for (int e = tid; e < n * NB; e += NT) {
+            const int i = e / NB, sidx = e - i * NB;
+            W[e] = sidx < nb ? B[(size_t)i * n + k0 + sidx] : s_zero<T>();
+        }
+        __syncthreads();
+        // eliminate the panel in LDS
+        for (int t = 0; t < nb; ++t) {
+            double best = -1.0;
+            int bidx = n;
+            for (int i = tid; i < n; i += NT) {
+                const double a = pinv[i] < 0 ? s_abs(W[i * NB + t]) : -1.0;
+                if (a > best) { best = a; bidx = i; }
+            }
+            const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
+            const T piv = W[p * NB + t];
+            if (s_abs1(piv) == 0.0) ok = false;
+            const T pivinv = s_div(s_one<T>(), piv);
+            if (tid < NB) pr[tid] = (tid == t) ? pivinv : s_mul(W[p * NB + tid], pivinv);
+            __syncthreads();
+            if (tid == 0) { perm[k0 + t] = p; pinv[p] = k0 + t; }
+            for (int i = tid; i < n; i += NT) {
+                T* w = W + i * NB;
+                if (i == p) {
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) w[s2] = pr[s2];
+                } else {
+                    const T f = w[t];
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) w[s2] = s_sub(s2 == t ? s_zero<T>() : w[s2], s_mul(f, pr[s2]));
+                }
+            }
+            __syncthreads();
+        }
+        // rank-nb update of the columns outside the panel
+        if (groups > 1) {
+            // one column per thread: read its pivot-row entries before any thread writes
+            const int j = jc;
+            const bool mine = g < groups && !(j >= k0 && j < k0 + nb);
+            T R[NB];
+#pragma unroll
+            for (int s2 = 0; s2 < NB; ++s2)
+                R[s2] = (s2 < nb && mine) ? B[(size_t)perm[k0 + s2] * n + j] : s_zero<T>();
+            __syncthreads();
+            if (mine) panel_update_column<T, NB>(B, n, j, g, groups, k0, nb, W, pinv, R);
+        } else if (g == 0) {
+            // each column has one owner thread, so it reads and updates the column alone
+            for (int j = jc; j < n; j += nc) {
+                if (j >= k0 && j < k0 + nb) continue;
+                T R[NB];
+#pragma unroll
+                for (int s2 = 0; s2 < NB; ++s2) R[s2] = s2 < nb ? B[(size_t)perm[k0 + s2] * n + j] : s_zero<T>();
+                panel_update_column<T, NB>(B, n, j, 0, 1, k0, nb, W, pinv, R);
+            }
+        }
+        __syncthreads();
+        // the panel columns take W
+        for (int e = tid; e < n * nb; e += NT) {
+            const int i = e / nb, sidx = e - i * nb;
+            B[(size_t)i * n + k0 + sidx] = W[i * NB + sidx];
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// The widest panel that fits in GJ_PANEL_BYTES of LDS.
 template <typename T>
-__device__ int rhi(T* S, T* B, int n, int maxit, double tol, T* prow, T* fcol, int* perm, double2* lds,
-                   double* ldsd, int* ldsi) {
+__device__ bool gj_invert(T* __restrict__ B, int n, T* __restrict__ prow, int* __restrict__ perm,
+                          T* __restrict__ fcol, int* __restrict__ pinv, T* __restrict__ W, double* ldsd,
+                          int* ldsi) {
+    const size_t row = (size_t)n * sizeof(T);
+    if (row * 8 <= (size_t)GJ_PANEL_BYTES) return gj_invert_blocked<T, 8>(B, n, perm, fcol, pinv, W, ldsd, ldsi);
+    if (row * 4 <= (size_t)GJ_PANEL_BYTES) return gj_invert_blocked<T, 4>(B, n, perm, fcol, pinv, W, ldsd, ldsi);
+    if (row * 2 <= (size_t)GJ_PANEL_BYTES) return gj_invert_blocked<T, 2>(B, n, perm, fcol, pinv, W, ldsd, ldsi);
+    return gj_invert_unblocked<T>(B, n, prow, perm, fcol, pinv, ldsd, ldsi);
+}
+
+static_assert((RHI_MAX + GJ_NB) * sizeof(double2) + RHI_MAX * sizeof(int) <= NT * sizeof(Aff2<double2>),
+              "the RHi pivot row, pivot column and permutation live in the scan LDS");
+
+template <typename T>
+__device__ int rhi(T* S, T* B, int n, int maxit, double tol, T* prow, int* perm, void* lds, void* panel,
+                   double2* red, double* ldsd, int* ldsi) {
+    if (n > RHI_MAX) return -1;
+    T* fcol = (T*)lds + GJ_NB;              // the blocked sweep keeps its pivot row just before
+    int* pinv = (int*)(fcol + n);
     bool last = false;
     for (int it = 1; it <= maxit; ++it) {
         for (int e = threadIdx.x; e < n * n; e += NT) B[e] = S[e];
         __syncthreads();
-        const bool ok = gj_invert<T>(B, n, prow, fcol, perm, ldsd, ldsi);
+        const bool ok = gj_invert<T>(B, n, prow, perm, fcol, pinv, (T*)panel, ldsd, ldsi);
         if (!ok) return -it;
         double ch = 0.0, nm = 0.0;
-        for (int e = threadIdx.x; e < n * n; e += NT) {
-            const T sn = s_scale(s_add(S[e], B[e]), 0.5);
-            ch += s_abs2(s_sub(sn, S[e]));
-            nm += s_abs2(sn);
-            S[e] = sn;
+        for (int k = 0; k < n; ++k) {
+            const T* inv_row = B + (size_t)perm[k] * n;     // row k of S^{-1}, columns permuted
+            T* srow = S + (size_t)k * n;
+            for (int m = threadIdx.x; m < n; m += NT) {
+                const T sn = s_scale(s_add(srow[m], inv_row[pinv[m]]), 0.5);
+                ch += s_abs2(s_sub(sn, srow[m]));
+                nm += s_abs2(sn);
+                srow[m] = sn;
+            }
         }
-        const double2 r = block_sum<NT>(mk(ch, nm), lds);
+        const double2 r = block_sum<NT>(mk(ch, nm), red);
         const double change = sqrt(r.x) / sqrt(r.y);
         if (change <= tol || last) return it;
         if (change <= RHI_NEAR) last = true;
@@ -481,6 +628,7 @@ struct Smem {
     double* redd;     // NT/64
     int* redi;        // NT/64
     void* scan;       // NT affine maps
+    void* panel;      // GJ_PANEL_BYTES: the Gauss-Jordan panel of RHi
 };
 
 // ---------------------------------------------------------------- step 3: p
@@ -738,7 +886,7 @@ __device__ int inner_coeffs(const JobDesc& J, const NestPtrs& P, int k, int m, T
         S[e] = val;
     }
     __syncthreads();
-    const int it = rhi<T>(S, B, m, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, sm.red, sm.redd, sm.redi);
+    const int it = rhi<T>(S, B, m, J.max_rhi, J.rhi_tol, (T*)P.prow, P.perm, sm.scan, sm.panel, sm.red, sm.redd, sm.redi);
     __syncthreads();
     for (int j = tid; j < m; j += NT) s_e1[j] = S[(size_t)j * m];
     __syncthreads();
@@ -769,7 +917,7 @@ __device__ int nonnested_coeffs(const JobDesc& J, const NestPtrs& P, int k, T* o
         S[e] = v;
     }
     __syncthreads();
-    const int it = rhi<T>(S, B, k, J.max_rhi, J.rhi_tol, (T*)P.prow, (T*)P.fcol, P.perm, sm.red, sm.redd, sm.redi);
+    const int it = rhi<T>(S, B, k, J.max_rhi, J.rhi_tol, (T*)P.prow, P.perm, sm.scan, sm.panel, sm.red, sm.redd, sm.redi);
     __syncthreads();
     for (int i = tid; i < k; i += NT) out[i] = S[(size_t)i * k];
     __syncthreads();
@@ -1036,9 +1184,11 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm, fl
             int kt = (int)ceil(ks / LEARN_DK) * LEARN_DK;
             kt = max(kt, j + LEARN_DK);
             if (learned && kt < J.k) J.status[ST_KTARGET] = kt;
-            // nearest power of two (geometric), at least 8
+            // largest power of two not above ell* (at least 8): a start below the
+            // needed size costs one more doubling at small size, one above a
+            // dense RHi step eight times dearer per doubling
             int es = 8;
-            while (es * 1.4142135623730951 < ls && es < J.lcap) es *= 2;
+            while (2.0 * es <= 1.05 * ls && es < J.lcap) es *= 2;
             J.status[ST_ELLSTART] = es;
         }
         __syncthreads();
@@ -1113,12 +1263,14 @@ __global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int
     __shared__ double redd[NT / 64];
     __shared__ int redi[NT / 64];
     __shared__ Aff2<double2> scan_lds[NT];
+    __shared__ double2 panel_lds[GJ_PANEL_BYTES / sizeof(double2)];
     __shared__ float net_out[2];
     Smem sm;
     sm.red = red;
     sm.redd = redd;
     sm.redi = redi;
     sm.scan = scan_lds;
+    sm.panel = panel_lds;
     const JobDesc& J = jobs[blockIdx.x];
     if (J.two_sided) nested_job<double2>(J, mode, j, sm, net_out);
     else nested_job<double>(J, mode, j, sm, net_out);
@@ -1159,11 +1311,13 @@ __global__ __launch_bounds__(NT) void label_kernel(JobDesc* jobs) {
     __shared__ double redd[NT / 64];
     __shared__ int redi[NT / 64];
     __shared__ Aff2<double2> scan_lds[NT];
+    __shared__ double2 panel_lds[GJ_PANEL_BYTES / sizeof(double2)];
     Smem sm;
     sm.red = red;
     sm.redd = redd;
     sm.redi = redi;
     sm.scan = scan_lds;
+    sm.panel = panel_lds;
     const JobDesc& J = jobs[blockIdx.x];
     if (J.two_sided) label_point<double2>(J, blockIdx.y, sm);
     else label_point<double>(J, blockIdx.y, sm);

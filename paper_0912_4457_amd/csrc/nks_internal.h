@@ -145,6 +145,7 @@ struct JobDesc {
     double* label;      // label mode output (LABEL_WORDS doubles), or null
 };
 
+constexpr int RHI_MAX = 1024;    // largest dense Roberts-Higham matrix (inner ell, or k when non-nested)
 constexpr int CKPT_DK = 100;     // outer iterations between plain k-checkpoints
 constexpr int LEARN_K0 = 100;    // probe length of the learned policy (features of H_{k0})
 constexpr int LEARN_DK = 20;     // granularity of the learned k and of its verification

@@ -20,10 +20,12 @@ changes at each k_i.  For a tolerance tau:
 
 The network (16 -> 64 -> 64 -> 2, SiLU) regresses (log10 k*, log10 ell*)
 from the normalised features; it is trained with nks_mlp_backward and
-nks_mlp_adam_step on the GPU.  After training the k output is shifted by
-the 85th percentile of the held-out under-prediction, so that most
-predictions pass verification (a miss costs a fall-back, an over-shoot
-only extra outer steps).
+nks_mlp_adam_step on the GPU.  After training the outputs are shifted
+against the asymmetric costs of a wrong guess: k up by the 85th percentile
+of the held-out under-prediction (a short k costs a fall-back to the
+checkpoints, a long one only extra outer steps), ell down to the 10th
+percentile (a small start costs one more doubling at small size, a large
+one a dense Roberts-Higham step eight times dearer per doubling).
 
     python -m paper_0912_4457_amd.policy --out policy_net.json --lattices 120
 """
@@ -229,6 +231,42 @@ def label_configs(ctx, cfgs, sources_per_lattice: int = 4, log=None):
     return np.asarray(rows), np.asarray(krefs), np.asarray(groups)
 
 
+def compare(ctx, cfgs, tols=(1e-8, 1e-10), sources: int = 2, log=None):
+    """Run the plain (DOUBLING) and the learned policies on the same jobs,
+    one job per call; returns records with k_used, ell_used, status and the
+    device time of each call (outer loop with checkpoints, nested step, lift)."""
+    import nks_inputs as I
+    from . import POLICY_DOUBLING, POLICY_LEARNED, Lattice, sign_apply
+    out = []
+    for c in cfgs:
+        lat = Lattice(ctx, c["dims"], I.su3_links(c["dims"], c["eps"], c["seed"]), m0=c["m0"], mu=c["mu"])
+        rng = np.random.default_rng(c["seed"] + 5)
+        V = int(np.prod(c["dims"]))
+        bs = [I.point_source(c["dims"], int(rng.integers(4)), int(rng.integers(3)), int(rng.integers(V))).ravel()
+              for _ in range(sources)]
+        for tol in tols:
+            for b in bs:
+                rec = dict(cfg=c, tol=tol)
+                xs = {}
+                for name, pol in (("plain", POLICY_DOUBLING), ("learned", POLICY_LEARNED)):
+                    sign_apply(lat, b, k=1400, ell=256, tol=tol, k_policy=pol, ell_policy=pol)    # warm-up
+                    x, st = sign_apply(lat, b, k=1400, ell=256, tol=tol, k_policy=pol, ell_policy=pol)
+                    rec[name] = dict(k=st["k_used"], ell=st["ell_used"], status=st["status"],
+                                     ms=st["ms_outer"] + st["ms_nested"] + st["ms_lift"])
+                    xs[name] = x.cpu().numpy()
+                rec["rel_learned_vs_plain"] = float(np.linalg.norm(xs["learned"] - xs["plain"]) /
+                                                    np.linalg.norm(xs["plain"]))
+                out.append(rec)
+                if log:
+                    log(f"[policy] {c['dims']} eps {c['eps']:.2f} m0 {c['m0']:.2f} mu {c['mu']} tol {tol:g}: "
+                        f"k {rec['plain']['k']} -> {rec['learned']['k']}, ell {rec['plain']['ell']} -> "
+                        f"{rec['learned']['ell']}, ms {rec['plain']['ms']:.1f} -> {rec['learned']['ms']:.1f}, "
+                        f"status {rec['plain']['status']}/{rec['learned']['status']}, "
+                        f"rel diff {rec['rel_learned_vs_plain']:.1e}")
+        lat.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=DEFAULT_PATH)
@@ -236,6 +274,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=31)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--labels", default=None, help="save/load the label rows here (.npz)")
+    ap.add_argument("--compare", type=int, default=0, help="held-out lattices for a plain-vs-learned comparison")
     args = ap.parse_args(argv)
     import paper_0912_4457_amd as nks
 
@@ -259,15 +298,30 @@ def main(argv=None):
     pred = predict(ctx, params, fm, fs, tm, ts, X[held])
     res = T[held] - pred
     shift = float(np.quantile(res[:, 0], 0.85)) if len(res) else 0.0
+    shift_ell = float(np.quantile(res[:, 1], 0.10)) if len(res) else 0.0
     tm_shift = tm.copy()
     tm_shift[0] += max(shift, 0.0)
+    tm_shift[1] += min(shift_ell, 0.0)
     rms = np.sqrt(np.mean(res ** 2, axis=0)) if len(res) else np.zeros(2)
     meta = dict(samples_train=int((~held).sum()), samples_held=int(held.sum()), label_rows=int(len(rows)),
                 lattices=args.lattices, seed=args.seed, steps=args.steps, loss=hist,
                 held_rms_log10_k=float(rms[0]), held_rms_log10_ell=float(rms[1]), k_shift_log10=max(shift, 0.0),
+                ell_shift_log10=min(shift_ell, 0.0),
                 tols=list(TOLS))
     log(f"[policy] held-out rms log10 k {rms[0]:.4f}, log10 ell {rms[1]:.4f}, k shift {shift:.4f}")
-    save(args.out, pack(params, fm, fs, tm_shift, ts), meta)
+    blob = pack(params, fm, fs, tm_shift, ts)
+    if args.compare:
+        from . import policy_load
+        policy_load(ctx, blob)
+        recs = compare(ctx, sample_configs(args.compare, args.seed + 1), log=log)
+        kp = sum(r["plain"]["k"] for r in recs)
+        kl = sum(r["learned"]["k"] for r in recs)
+        mp = sum(r["plain"]["ms"] for r in recs)
+        ml = sum(r["learned"]["ms"] for r in recs)
+        meta["compare"] = dict(lattices=args.compare, k_plain=kp, k_learned=kl, ms_plain=mp, ms_learned=ml,
+                               max_rel_learned_vs_plain=max(r["rel_learned_vs_plain"] for r in recs))
+        log(f"[policy] held-out comparison: sum k {kp} -> {kl} ({kl / kp:.3f}), device ms {mp:.1f} -> {ml:.1f}")
+    save(args.out, blob, meta)
     log(f"[policy] wrote {args.out}")
     return 0
 

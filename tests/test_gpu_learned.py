@@ -165,3 +165,61 @@ def test_label_features_match_oracle(mu):
     assert f[9] == pytest.approx(np.mean(np.abs(kr.alpha)), rel=1e-9)
     assert f[10] == pytest.approx(np.mean(np.sqrt(np.abs(kr.beta * kr.gamma))), rel=1e-9)
     assert np.all(f[11:] == 0.0)
+
+
+# ---------------------------------------------------------------- trained network
+def _held_out_configs():
+    """Lattices the shipped network never saw (its training used seed 31 and
+    sample_configs draws seeds seed * 1000 + i), small enough for the oracle."""
+    from paper_0912_4457_amd import policy as P
+    cfgs = [c for c in P.sample_configs(40, 33) if np.prod(c["dims"]) <= 4096 and c["eps"] <= 0.38]
+    return cfgs[:4]
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_reference(i):
+    from oracle import dirac, policy
+    c = _held_out_configs()[i]
+    op = dirac.Operator(I.su3_links(c["dims"], c["eps"], c["seed"]), c["dims"], c["m0"], c["mu"])
+    b = _source(c)
+    y, info = policy.sign_apply_policy(op, b, 1e-12, k_max=1600, ell_max=256)
+    return y.ravel(), info
+
+
+def _source(c):
+    rng = np.random.default_rng(c["seed"] + 5)
+    return I.point_source(c["dims"], int(rng.integers(4)), int(rng.integers(3)),
+                          int(rng.integers(int(np.prod(c["dims"])))))
+
+
+def test_trained_network_gains_over_doubling():
+    """The shipped network against the plain policies on held-out lattices:
+    same accuracy against the oracle, less device time."""
+    import paper_0912_4457_amd as nks
+    c0 = ctx()
+    meta = nks.load_policy(c0)
+    assert meta["samples_train"] > 1000
+    rows = []
+    for i, c in enumerate(_held_out_configs()):
+        lat = nks.Lattice(c0, c["dims"], I.su3_links(c["dims"], c["eps"], c["seed"]), m0=c["m0"], mu=c["mu"])
+        b = _source(c).ravel()
+        y_ref, info = _oracle_reference(i)
+        assert info["converged"]
+        for tol in (1e-8, 1e-10):
+            r = {}
+            for name, pol in (("plain", DOUBLING), ("learned", LEARNED)):
+                nks.sign_apply(lat, b, k=1400, ell=256, tol=tol, k_policy=pol, ell_policy=pol)   # warm-up
+                x, st = nks.sign_apply(lat, b, k=1400, ell=256, tol=tol, k_policy=pol, ell_policy=pol)
+                assert st["status"] == 0, (c, tol, name, st)
+                err = rel(to_np(x), y_ref)
+                assert err <= 10 * tol, (c, tol, name, err)
+                r[name] = (st["k_used"], st["ms_outer"] + st["ms_nested"] + st["ms_lift"], err)
+            rows.append((c["dims"], c["mu"], tol, r))
+        lat.close()
+    ms_plain = sum(r["plain"][1] for *_, r in rows)
+    ms_learned = sum(r["learned"][1] for *_, r in rows)
+    for dims, mu, tol, r in rows:
+        print(f"{dims} mu={mu} tol={tol:g}: k {r['plain'][0]} -> {r['learned'][0]}, "
+              f"ms {r['plain'][1]:.1f} -> {r['learned'][1]:.1f}, err {r['plain'][2]:.1e} / {r['learned'][2]:.1e}")
+    print(f"device time plain {ms_plain:.1f} ms, learned {ms_learned:.1f} ms ({ms_learned / ms_plain:.2f})")
+    assert ms_learned <= 0.85 * ms_plain
