@@ -75,7 +75,9 @@ def golden_samples():
         return json.load(f)
 
 
-def make_jobs(nks, torch, ctx, precision):
+def make_jobs(nks, torch, ctx, precision, **policy):
+    """The 24 jobs of the workload; policy keys (k, ell, tol, k_policy,
+    ell_policy) override the fixed k = K, ell = ELL."""
     import nks_inputs as I
     links = I.su3_links(DIMS, EPS, LINK_SEED)
     lats, jobs = [], []
@@ -85,8 +87,10 @@ def make_jobs(nks, torch, ctx, precision):
         for spin in range(4):
             for colour in range(3):
                 b = torch.from_numpy(I.point_source(DIMS, spin, colour).ravel()).cuda()
-                jobs.append(dict(lat=lat, b=b, k=K, ell=ELL, precision=precision, mu=mu, spin=spin,
-                                 colour=colour, x=torch.empty_like(b)))
+                j = dict(lat=lat, b=b, k=K, ell=ELL, precision=precision, mu=mu, spin=spin,
+                         colour=colour, x=torch.empty_like(b))
+                j.update(policy)
+                jobs.append(j)
     return lats, jobs
 
 
@@ -132,6 +136,79 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
     torch.cuda.synchronize()
     errs = errors_vs_golden(jobs, xs, gold)
     return dict(seconds=dt, steps=steps, napps=len(jobs), prof=prof, stats=sts, errs=errs, tuned=tuned)
+
+
+def time_calls(nks, torch, jobs, steps, warmup, graph=True):
+    """Seconds for `steps` batched calls (no stats, so graph mode replays)."""
+    ctx = jobs[0]["lat"].ctx
+    ctx.tune_set("graph", int(graph))
+    for _ in range(warmup):
+        nks.sign_apply_batch(jobs, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nks.sign_apply_batch(jobs, stats=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.tune_set("graph", 1)
+    return dt
+
+
+def policy_paths(nks, torch, ctx, gold, steps):
+    """The same workload under the tolerance-driven policies: the plain
+    ell-doubling / k-checkpoint rules and the learned network, FP64 at the
+    workload's 1e-8 and mixed precision at 1e-6."""
+    nks.load_policy(ctx)
+    out = []
+    for name, prec, pol, tol in (("fp64_doubling", "fp64", 1, 1e-8), ("fp64_learned", "fp64", 2, 1e-8),
+                                 ("mixed_doubling", "mixed", 1, 1e-6), ("mixed_learned", "mixed", 2, 1e-6)):
+        lats, jobs = make_jobs(nks, torch, ctx, prec, k=1400, ell=256, tol=tol, k_policy=pol, ell_policy=pol)
+        dt = time_calls(nks, torch, jobs, steps, 1)
+        xs, sts = nks.sign_apply_batch(jobs, stats=True)
+        torch.cuda.synchronize()
+        errs = errors_vs_golden(jobs, xs, gold)
+        out.append({"path": name, "precision": prec, "tol": tol, "value": len(jobs) * steps / dt,
+                    "ms_per_step": dt / steps * 1e3,
+                    "max_rel_err_vs_oracle": max(errs) if errs else None,
+                    "k_used_mean": sum(s["k_used"] for s in sts) / len(sts),
+                    "ell_used": sorted(set(s["ell_used"] for s in sts)),
+                    "status": sorted(set(s["status"] for s in sts))})
+        log(f"[bench] {name}: {out[-1]['value']:.1f} app/s, err {out[-1]['max_rel_err_vs_oracle']}, "
+            f"k mean {out[-1]['k_used_mean']:.0f}")
+        for lat in lats:
+            lat.close()
+    return out
+
+
+def uneven_batch(nks, torch, ctx, steps):
+    """64 point sources over nine lattices (6^4, 8^4, 10^4 x mu in {0, 0.1,
+    0.3}) with tolerances 1e-6 / 1e-8, in one batched call: plain policies
+    eager and graph-replayed, and the learned policy graph-replayed."""
+    import numpy as np
+    import nks_inputs as I
+    rng = np.random.default_rng(64)
+    lats = []
+    for dims, seed in (((6, 6, 6, 6), 6601), ((8, 8, 8, 8), 8801), ((10, 10, 10, 10), 10401)):
+        u = I.su3_links(dims, EPS, seed)
+        for mu in (0.0, 0.1, 0.3):
+            lats.append(nks.Lattice(ctx, dims, u, m0=M0, mu=mu))
+    base = []
+    for i in range(64):
+        lat = lats[i % len(lats)]
+        b = torch.from_numpy(I.point_source(lat.dims, int(rng.integers(4)), int(rng.integers(3)),
+                                            int(rng.integers(lat.V))).ravel()).cuda()
+        base.append(dict(lat=lat, b=b, x=torch.empty_like(b), k=1400, ell=256,
+                         tol=float(rng.choice([1e-6, 1e-8])), precision="fp64"))
+    res = {"jobs": 64, "lattices": "6^4, 8^4, 10^4 x mu in {0, 0.1, 0.3}", "tolerances": [1e-6, 1e-8]}
+    nks.load_policy(ctx)
+    for name, pol, graph in (("doubling_eager", 1, False), ("doubling_graph", 1, True), ("learned_graph", 2, True)):
+        jobs = [dict(j, k_policy=pol, ell_policy=pol) for j in base]
+        dt = time_calls(nks, torch, jobs, steps, 1, graph=graph)
+        res[name] = {"value": 64 * steps / dt, "ms_per_call": dt / steps * 1e3}
+        log(f"[bench] uneven batch {name}: {res[name]['value']:.1f} app/s")
+    for lat in lats:
+        lat.close()
+    return res
 
 
 def stencil_large(nks, torch, ctx, precision):
@@ -208,6 +285,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the policy and uneven-batch sections")
     ap.add_argument("--probe", action="store_true",
                     help="short run of the main path only (for hardware-counter passes)")
     a = ap.parse_args()
@@ -239,6 +317,18 @@ def main():
     other = "mixed" if a.precision == "fp64" else "fp64"
     log(f"[bench] {other} path for comparison")
     other_run = run_path(nks, torch, ctx, other, max(2, a.steps // 2), 1, gold, profile=False)
+    graph_dt = None
+    lats_g, jobs_g = make_jobs(nks, torch, ctx, a.precision)
+    graph_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
+    eager_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=False)
+    for lat in lats_g:
+        lat.close()
+    paths = uneven = None
+    if not a.no_extra:
+        log("[bench] policy paths")
+        paths = policy_paths(nks, torch, ctx, gold, max(2, a.steps // 2))
+        log("[bench] uneven batch")
+        uneven = uneven_batch(nks, torch, ctx, 2)
     large = None
     if not a.no_large:
         log("[bench] stencil pass on a 32^4 lattice")
@@ -285,6 +375,10 @@ def main():
         "other_path": {"precision": other,
                        "value": other_run["napps"] * other_run["steps"] / other_run["seconds"],
                        "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None)},
+        "graph_replay": {"value": main_run["napps"] * a.steps / graph_dt,
+                         "eager_value": main_run["napps"] * a.steps / eager_dt},
+        "policy_paths": paths,
+        "uneven_batch": uneven,
         "stencil_large": large,
         "tuning": main_run["tuned"],
     }

@@ -160,9 +160,14 @@ int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
                    nks_stats* stats);
 
 /* Many jobs in one call: jobs on the same lattice share each stencil sweep
- * over the links; the whole launch sequence is captured once into a HIP
- * graph and replayed on later calls with the same job shapes.  stats is
- * NULL or an array of njobs entries (then the call waits for the stream). */
+ * over the links.  In graph mode (the default, tuning key "graph") a call
+ * without stats and without profiling captures its whole launch sequence
+ * into a HIP graph on a private stream, keyed by the job table (every
+ * pointer, size and option) and the workspace address, and later calls
+ * with the same key replay it on `stream` (up to 4 graphs are kept per
+ * context).  A call with stats runs eagerly.  stats is NULL or an array of
+ * njobs entries (then the call waits for the stream).  The library keeps a
+ * host copy of the job table until the next call on the context. */
 int nks_sign_apply_batch(nks_ctx* ctx, int njobs, const nks_job* jobs, void* ws,
                          size_t ws_bytes, void* stream, nks_stats* stats);
 
@@ -256,6 +261,9 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  *                0: 2D grid (site block, job)
  *   "split_dual" 1: the two-sided stencil computes A u and A^dagger t in
  *                separate workgroups; 0: one thread does both.
+ *   "graph"      1: capture and replay batched calls as HIP graphs (see
+ *                nks_sign_apply_batch); 0: launch eagerly.
+ * Read-only counters: "graph_captures", "graph_replays".
  * Results are identical bit for bit under every choice.  Unknown keys give
  * NKS_E_INVALID. */
 int nks_tune_set(nks_ctx* ctx, const char* key, int value);

@@ -32,6 +32,17 @@ struct nks_ctx {
     long long prof_count[NKS_K_COUNT] = {0, 0, 0, 0};
     Tuning tune;
     PolicyNet* net = nullptr;     // device copy of the learned-policy network (nks_policy_load)
+    // graph mode: captured launch sequences keyed by the job table they were captured for
+    int graph = 1;
+    hipStream_t cap = nullptr;    // private stream the sequences are captured on
+    struct Graph {
+        std::vector<char> key;
+        hipGraphExec_t exec = nullptr;
+        unsigned long long used = 0;
+    };
+    std::vector<Graph> graphs;
+    unsigned long long graph_clock = 0;
+    long long graph_captures = 0, graph_replays = 0;
 };
 
 struct nks_lattice {
@@ -283,11 +294,11 @@ double bytes_lift(const OuterLaunch& L, const Plan& P, int start) {
 
 enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1, PH_LABEL = 2 };
 
-// Enqueue the whole method for all jobs.  Events (if non-null) mark phase ends.
-int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s,
-            bool timed, int phase) {
+// Enqueue the whole method for all jobs; the job table must already be on the
+// device at the start of ws.  Events (when timed) mark phase ends.
+int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s,
+                    bool timed, int phase) {
     JobDesc* table = reinterpret_cast<JobDesc*>(ws);
-    HIP_TRY(ctx, hipMemcpyAsync(table, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
@@ -344,6 +355,69 @@ int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char
     }
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
+    return NKS_OK;
+}
+
+int enqueue(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s, bool timed,
+            int phase) {
+    HIP_TRY(ctx, hipMemcpyAsync(ws, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
+    return enqueue_kernels(ctx, P, descs, ws, s, timed, phase);
+}
+
+constexpr size_t GRAPH_CACHE = 4;
+
+// Graph mode: the kernel sequence of a batch is captured once (on a private
+// stream) and replayed; the job table is uploaded before every replay.  The
+// key is the table itself (every pointer, size and option of every job).
+int enqueue_graph(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s) {
+    std::vector<char> key(sizeof(JobDesc) * descs.size());
+    std::memcpy(key.data(), descs.data(), key.size());
+    auto put = [&key](const void* p, size_t n) {
+        key.insert(key.end(), static_cast<const char*>(p), static_cast<const char*>(p) + n);
+    };
+    const size_t wsaddr = reinterpret_cast<size_t>(ws);
+    put(&wsaddr, sizeof(wsaddr));
+    put(&ctx->tune, sizeof(ctx->tune));
+    for (const auto& gr : P.groups) {
+        // launch arguments taken by value at capture: operator parameters and link fields
+        const nks_lattice* lat = P.jobs[gr.first].lat;
+        put(&lat->kappa, sizeof(lat->kappa));
+        put(&lat->mu, sizeof(lat->mu));
+        put(&lat->links64, sizeof(lat->links64));
+        put(&lat->links32, sizeof(lat->links32));
+        put(&lat->g, sizeof(lat->g));
+    }
+    nks_ctx::Graph* hit = nullptr;
+    for (auto& g : ctx->graphs)
+        if (g.key == key) hit = &g;
+    if (!hit) {
+        if (!ctx->cap) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_kernels(ctx, P, descs, ws, ctx->cap, false, PH_ALL);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(ctx, NKS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(ctx, NKS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        if (ctx->graphs.size() >= GRAPH_CACHE) {
+            auto old = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                        [](const nks_ctx::Graph& a, const nks_ctx::Graph& b) { return a.used < b.used; });
+            HIP_TRY(ctx, hipStreamSynchronize(s));   // an evicted graph may still be running on s
+            (void)hipGraphExecDestroy(old->exec);
+            ctx->graphs.erase(old);
+        }
+        ctx->graphs.push_back({key, exec, 0});
+        hit = &ctx->graphs.back();
+        ++ctx->graph_captures;
+    } else {
+        ++ctx->graph_replays;
+    }
+    hit->used = ++ctx->graph_clock;
+    HIP_TRY(ctx, hipMemcpyAsync(ws, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipGraphLaunch(hit->exec, s));
     return NKS_OK;
 }
 
@@ -409,6 +483,7 @@ int nks_create(int device, nks_ctx** out) {
     c->device = device;
     if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = atoi(e) != 0;
     if (const char* e = getenv("NKS_SPLIT_DUAL")) c->tune.split_dual = atoi(e) != 0;
+    if (const char* e = getenv("NKS_GRAPH")) c->graph = atoi(e) != 0;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return NKS_E_HIP; }
     *out = c;
@@ -425,6 +500,8 @@ void nks_destroy(nks_ctx* ctx) {
     }
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->net) (void)hipFree(ctx->net);
+    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
 
@@ -533,7 +610,8 @@ int nks_sign_apply_batch(nks_ctx* ctx, int njobs, const nks_job* jobs, void* ws,
     for (const auto& jp : P.jobs) descs.push_back(make_desc(ctx, jp, w, jobs[jp.idx].b, jobs[jp.idx].x));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool timed = stats != nullptr;
-    rc = enqueue(ctx, P, descs, w, s, timed, PH_ALL);
+    if (ctx->graph && !timed && !ctx->prof) rc = enqueue_graph(ctx, P, descs, w, s);
+    else rc = enqueue(ctx, P, descs, w, s, timed, PH_ALL);
     if (rc) return rc;
     if (stats) {
         HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -752,6 +830,7 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
     const std::string k(key);
     if (k == "xcd_map") ctx->tune.xcd_map = value != 0;
     else if (k == "split_dual") ctx->tune.split_dual = value != 0;
+    else if (k == "graph") ctx->graph = value != 0;
     else return fail(ctx, NKS_E_INVALID, "unknown tuning key " + k);
     return NKS_OK;
 }
@@ -761,6 +840,9 @@ int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
     const std::string k(key);
     if (k == "xcd_map") *value = ctx->tune.xcd_map;
     else if (k == "split_dual") *value = ctx->tune.split_dual;
+    else if (k == "graph") *value = ctx->graph;
+    else if (k == "graph_captures") *value = (int)ctx->graph_captures;
+    else if (k == "graph_replays") *value = (int)ctx->graph_replays;
     else return fail(ctx, NKS_E_INVALID, "unknown tuning key " + k);
     return NKS_OK;
 }
