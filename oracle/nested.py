@@ -73,20 +73,30 @@ def tridiag_matvec(sub, diag, sup, v):
 
 
 def ritz_extremes(alpha, beta, gamma, hermitian: bool):
-    """(z_min, z_max) = (min |theta|, max |theta|) over the Ritz values of H_k."""
+    """(z_min, z_max) of the Ritz values of H_k, the spectrum estimate behind
+    p_opt of Sec. 4.1 (Eq. popt).
+
+    z_max = max |theta|.  Hermitian: z_min is the second smallest |theta|.
+    The Ritz values of a Krylov space are the zeros of the Lanczos
+    polynomial, and between two of them lies at least one eigenvalue of A,
+    so the spectral gap of the indefinite A around 0 holds at most one Ritz
+    value; that one can sit anywhere in the gap (near 0 for some sources)
+    and says nothing about A's smallest |lambda|.  The second smallest
+    |theta| lies outside the gap.  Two-sided: min |theta| (no such
+    interlacing for a non-normal H_k)."""
     if hermitian:
         if len(alpha) == 1:
             w = np.asarray(alpha, float)
         else:
             w = sla.eigh_tridiagonal(np.asarray(alpha, float), np.asarray(beta, float),
                                      eigvals_only=True)
-    else:
-        k = len(alpha)
-        h = np.diag(np.asarray(alpha, complex))
-        if k > 1:
-            h += np.diag(np.asarray(beta, complex), -1) + np.diag(np.asarray(gamma, complex), 1)
-        w = np.linalg.eigvals(h)
-    z = np.abs(w)
+        z = np.sort(np.abs(w))
+        return float(z[1] if z.size > 1 else z[0]), float(z[-1])
+    k = len(alpha)
+    h = np.diag(np.asarray(alpha, complex))
+    if k > 1:
+        h += np.diag(np.asarray(beta, complex), -1) + np.diag(np.asarray(gamma, complex), 1)
+    z = np.abs(np.linalg.eigvals(h))
     return float(z.min()), float(z.max())
 
 

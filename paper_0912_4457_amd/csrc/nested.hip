@@ -401,8 +401,6 @@ __device__ double find_eig(const double2* d, const double2* sub, int k, int m, d
     return 0.5 * (lo + hi);
 }
 
-// Dense in-place inversion of the n x n row-major matrix B (Gauss-Jordan,
-// partial pivoting).  Returns false if a pivot is exactly zero.
 // In-place Gauss-Jordan inversion with partial pivoting and implicit row
 // interchanges (the pivot rows are recorded, not moved).  After the sweep
 // B[perm[k]][pinv[m]] = (A^{-1})[k][m], with perm[k] the pivot row of column
@@ -663,13 +661,20 @@ __device__ void estimate_extremes(const JobDesc& J, const NestPtrs& P, int k, co
         const double l1 = find_eig(dd, ee, k, 1, G, pivmin, sm.redd);
         const double lk = find_eig(dd, ee, k, k, G, pivmin, sm.redd);
         zmax = fmax(fabs(l1), fabs(lk));
-        if (c0 == 0) zmin = fabs(l1);
-        else if (c0 == k) zmin = fabs(lk);
-        else {
-            const double ln = find_eig(dd, ee, k, c0, G, pivmin, sm.redd);
-            const double lp = find_eig(dd, ee, k, c0 + 1, G, pivmin, sm.redd);
-            zmin = fmin(fabs(ln), fabs(lp));
+        if (k == 1) { zmin = fabs(l1); return; }
+        // z_min: the second smallest |theta|.  Between two Ritz values lies an
+        // eigenvalue of A, so the gap of A around 0 holds at most one Ritz value,
+        // which may sit anywhere in it; the second smallest lies outside.  The
+        // two smallest |theta| are among the two largest negative and the two
+        // smallest positive Ritz values (indices c0 - 1 .. c0 + 2).
+        double z1 = INFINITY, z2 = INFINITY;
+        for (int m = c0 - 1; m <= c0 + 2; ++m) {
+            if (m < 1 || m > k) continue;
+            const double a = fabs(m == 1 ? l1 : (m == k ? lk : find_eig(dd, ee, k, m, G, pivmin, sm.redd)));
+            if (a < z1) { z2 = z1; z1 = a; }
+            else if (a < z2) z2 = a;
         }
+        zmin = z2;
         return;
     }
     // power iteration for z_max, inverse iteration (LU of H_k) for z_min; each

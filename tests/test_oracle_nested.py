@@ -200,13 +200,29 @@ def test_error_estimate_tracks_true_error():
         assert 0.1 * true < est < 10 * true
 
 
-def test_ritz_extremes_hermitian_and_general_agree():
+def test_ritz_extremes_match_dense_eigenvalues():
     op = _op(0.0)
     kr = krylov.lanczos(op.matvec, I.gaussian_source(op.dims, 6).ravel(), 40)
-    a = nested.ritz_extremes(kr.alpha, kr.beta, kr.beta, True)
+    z = np.sort(np.abs(np.linalg.eigvalsh(kr.H().real)))
+    assert np.allclose(nested.ritz_extremes(kr.alpha, kr.beta, kr.beta, True), (z[1], z[-1]), rtol=1e-10)
     b = nested.ritz_extremes(kr.alpha.astype(complex), kr.beta.astype(complex),
                              kr.beta.astype(complex), False)
-    assert np.allclose(a, b, rtol=1e-10)
+    assert np.allclose(b, (z[0], z[-1]), rtol=1e-10)
+
+
+def test_ritz_extremes_skip_the_one_ritz_value_in_the_gap():
+    # A = diag(+-[0.1 .. 1]) with symmetric weights: every odd-size H_k has the
+    # Ritz value 0 inside the gap (-0.1, 0.1); no other Ritz value can be there
+    lam = np.concatenate([np.linspace(0.1, 1.0, 50), -np.linspace(0.1, 1.0, 50)])
+    b = np.ones(100) / 10.0
+    kr = krylov.lanczos(lambda v: lam * v, b, 12)
+    for k in (5, 7, 11):                 # odd leading sections of H_12
+        al, be = kr.alpha[:k], kr.beta[:k - 1]
+        w = np.linalg.eigvalsh(np.diag(al) + np.diag(be, 1) + np.diag(be, -1))
+        assert np.abs(w).min() < 1e-12
+        zmin, zmax = nested.ritz_extremes(al, be, be, True)
+        assert 0.1 <= zmin <= 1.0 and zmax <= 1.0 + 1e-12
+        assert np.sum(np.abs(w) < 0.1) == 1
 
 
 def test_pure_gauge_nested_full_method():
