@@ -82,8 +82,9 @@ def ritz_extremes(alpha, beta, gamma, hermitian: bool):
     so the spectral gap of the indefinite A around 0 holds at most one Ritz
     value; that one can sit anywhere in the gap (near 0 for some sources)
     and says nothing about A's smallest |lambda|.  The second smallest
-    |theta| lies outside the gap.  Two-sided: min |theta| (no such
-    interlacing for a non-normal H_k)."""
+    |theta| lies outside the gap.  Two-sided: the same rule, without the
+    interlacing theorem behind it (a non-normal H_k has none); a single
+    Ritz value near the origin is seen there too."""
     if hermitian:
         if len(alpha) == 1:
             w = np.asarray(alpha, float)
@@ -96,8 +97,8 @@ def ritz_extremes(alpha, beta, gamma, hermitian: bool):
     h = np.diag(np.asarray(alpha, complex))
     if k > 1:
         h += np.diag(np.asarray(beta, complex), -1) + np.diag(np.asarray(gamma, complex), 1)
-    z = np.abs(np.linalg.eigvals(h))
-    return float(z.min()), float(z.max())
+    z = np.sort(np.abs(np.linalg.eigvals(h)))
+    return float(z[1] if z.size > 1 else z[0]), float(z[-1])
 
 
 class NestedInfo(dict):

@@ -715,21 +715,51 @@ __device__ void estimate_extremes(const JobDesc& J, const NestPtrs& P, int k, co
     __shared__ int info0;
     if (tid == 0) info0 = gttrf<T>(k, lf, u0, u1, u2, P.piv);
     __syncthreads();
-    for (int i = tid; i < k; i += NT) x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+    // z_min: the second smallest |theta| (a single Ritz value can stray near
+    // the origin), by inverse subspace iteration on two vectors with
+    // Gram-Schmidt: the diagonal of R grows like 1/|theta_1|, 1/|theta_2|
+    T* x2 = (T*)P.vp;
+    T* y2 = (T*)P.wp;
+    for (int i = tid; i < k; i += NT) {
+        x[i] = s_from<T>(mk(1.0 + 0.5 * (double)i / (double)k, 0.0));
+        x2[i] = s_from<T>(mk((i & 1) ? -1.0 : 1.0, 0.25 * (double)(i % 3)));
+    }
     __syncthreads();
-    if (info0 == 0) {
+    if (info0 == 0 && k >= 2) {
         const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
-        lsum = 0.0;
+        double l2sum = 0.0;
+        // orthonormal start
         nx = sqrt(block_norm2<T>(x, k, sm.red));
-        for (int it = 0; it < NIT; ++it) {
-            for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
+        for (int i = tid; i < k; i += NT) x[i] = s_scale(x[i], 1.0 / nx);
+        __syncthreads();
+        {
+            const T h = block_dot<T>(x, x2, k, sm.red);
+            for (int i = tid; i < k; i += NT) x2[i] = s_sub(x2[i], s_mul(h, x[i]));
             __syncthreads();
-            solve_n<T>(F, k, x, (T*)P.t, y, sm.scan);
-            nx = sqrt(block_norm2<T>(y, k, sm.red));
-            if (it >= NIT - NAVG) lsum += log(nx);
-            T* sw_ = x; x = y; y = sw_;
+            const double n2 = sqrt(block_norm2<T>(x2, k, sm.red));
+            for (int i = tid; i < k; i += NT) x2[i] = s_scale(x2[i], 1.0 / n2);
+            __syncthreads();
         }
-        zmin = exp(-lsum / NAVG);
+        lsum = 0.0;
+        for (int it = 0; it < NIT; ++it) {
+            solve_n<T>(F, k, x, (T*)P.t, y, sm.scan);
+            solve_n<T>(F, k, x2, (T*)P.t, y2, sm.scan);
+            const double n1 = sqrt(block_norm2<T>(y, k, sm.red));
+            for (int i = tid; i < k; i += NT) y[i] = s_scale(y[i], 1.0 / n1);
+            __syncthreads();
+            const T h = block_dot<T>(y, y2, k, sm.red);
+            for (int i = tid; i < k; i += NT) y2[i] = s_sub(y2[i], s_mul(h, y[i]));
+            __syncthreads();
+            const double n2 = sqrt(block_norm2<T>(y2, k, sm.red));
+            for (int i = tid; i < k; i += NT) y2[i] = s_scale(y2[i], 1.0 / n2);
+            __syncthreads();
+            if (it >= NIT - NAVG) { lsum += log(n1); l2sum += log(n2); }
+            T* sw_ = x; x = y; y = sw_;
+            sw_ = x2; x2 = y2; y2 = sw_;
+        }
+        zmin = exp(-l2sum / NAVG);
+    } else if (info0 == 0) {
+        zmin = s_abs(d[0]);
     } else {
         zmin = zmax * 1e-3;
     }

@@ -44,11 +44,18 @@ def test_nested_step_matches_oracle_at_given_p(case):
     if herm:
         tol = 1e-11
     else:
-        # the two-sided inner recurrence amplifies rounding: on the near-critical
-        # 8^4 H_k a 1e-16 relative change of alpha moves the oracle's own c by
-        # 1.3e-9; require agreement well inside the nested approximation error
-        c_nn, _ = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, herm, k)
-        tol = max(1e-9, 0.5 * rel(c_ref, c_nn))
+        # the two-sided inner recurrence amplifies rounding (on the near-critical
+        # 8^4 H_k a rounding-size change of alpha moves the oracle's own c by
+        # up to ~3e-9): measure that sensitivity and allow ten times it, since
+        # the GPU rounds differently in every LU sweep, inner step and inversion
+        # (two-ulp changes of every alpha; the response varies by 10x between draws)
+        resp = 0.0
+        for seed_ in (1, 2, 3):
+            rng = np.random.default_rng(seed_)
+            a2 = kr.alpha * (1 + 4e-16 * rng.choice([-1.0, 1.0], kr.alpha.shape))
+            c_pert, _ = nested.nested_coefficients(a2, kr.beta, kr.gamma, herm, ell, p=info["p"])
+            resp = max(resp, rel(c_pert, c_ref))
+        tol = max(1e-9, 10 * resp)
     assert rel(c_gpu, c_ref) <= tol
 
 

@@ -207,7 +207,7 @@ def test_ritz_extremes_match_dense_eigenvalues():
     assert np.allclose(nested.ritz_extremes(kr.alpha, kr.beta, kr.beta, True), (z[1], z[-1]), rtol=1e-10)
     b = nested.ritz_extremes(kr.alpha.astype(complex), kr.beta.astype(complex),
                              kr.beta.astype(complex), False)
-    assert np.allclose(b, (z[0], z[-1]), rtol=1e-10)
+    assert np.allclose(b, (z[1], z[-1]), rtol=1e-10)
 
 
 def test_ritz_extremes_skip_the_one_ritz_value_in_the_gap():
