@@ -317,7 +317,9 @@ def main():
     other = "mixed" if a.precision == "fp64" else "fp64"
     log(f"[bench] {other} path for comparison")
     other_run = run_path(nks, torch, ctx, other, max(2, a.steps // 2), 1, gold, profile=False)
-    graph_dt = None
+    if main_run["tuned"]:                       # the comparison path re-tuned the context
+        for k_, v_ in main_run["tuned"]["choice"].items():
+            ctx.tune_set(k_, v_)
     lats_g, jobs_g = make_jobs(nks, torch, ctx, a.precision)
     graph_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
     eager_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=False)

@@ -246,6 +246,8 @@ int nks_policy_load(nks_ctx* ctx, const float* blob, int nfloats);
  *   [76, 316)  for each k_i, the relative coefficient change of the ell
  *              doublings 16->32, 32->64, 64->128, 128->256 (NaN once the
  *              doubling stopped).
+ * Jobs at mu != 0 (two-sided) give NKS_E_UNSUPPORTED: such label runs are
+ * switched off until a GPU fault seen in one of them is explained.
  * Every k_i runs in a workgroup of its own with its own scratch (about
  * 61 times the nested scratch of a sign application per job).
  * Allocates its own workspace, uses the null stream and waits. */
@@ -258,9 +260,13 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
 /* Launch-shape choices of the outer passes, per context (an autotuner sets
  * them after timing the alternatives):
  *   "xcd_map"    1: 1D grid that keeps every job of a site block on one XCD
+ *                2: 1D grid that gives each XCD whole jobs (all site blocks)
  *                0: 2D grid (site block, job)
  *   "split_dual" 1: the two-sided stencil computes A u and A^dagger t in
  *                separate workgroups; 0: one thread does both.
+ *   "min_waves"  1, 3 or 4: register budget of the stencil kernels for that
+ *                many resident waves per SIMD (1 = unlimited; more waves
+ *                hide more latency, fewer registers may spill)
  *   "graph"      1: capture and replay batched calls as HIP graphs (see
  *                nks_sign_apply_batch); 0: launch eagerly.
  * Read-only counters: "graph_captures", "graph_replays".

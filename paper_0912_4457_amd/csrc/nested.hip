@@ -401,6 +401,15 @@ __device__ double find_eig(const double2* d, const double2* sub, int k, int m, d
     return 0.5 * (lo + hi);
 }
 
+// Pivot search key: rows already used never win; every unused row is a
+// candidate even when its entry is NaN (then it only wins if nothing else
+// can), so the chosen pivot row is always a valid unused row and a NaN matrix
+// fails the sweep (ok = false) instead of indexing row n.
+__device__ inline double pivot_weight(int used_as, double a) {
+    if (used_as >= 0) return -1.0;
+    return (a >= 0.0) ? a : -0.5;
+}
+
 // In-place Gauss-Jordan inversion with partial pivoting and implicit row
 // interchanges (the pivot rows are recorded, not moved).  After the sweep
 // B[perm[k]][pinv[m]] = (A^{-1})[k][m], with perm[k] the pivot row of column
@@ -424,12 +433,12 @@ __device__ bool gj_invert_unblocked(T* __restrict__ B, int n, T* __restrict__ pr
         for (int i = tid; i < n; i += NT) {
             const T v = B[(size_t)i * n + kk];
             fcol[i] = v;
-            const double a = pinv[i] < 0 ? s_abs(v) : -1.0;
+            const double a = pivot_weight(pinv[i], s_abs(v));
             if (a > best) { best = a; bidx = i; }
         }
         const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
         const T piv = fcol[p];
-        if (s_abs1(piv) == 0.0) ok = false;
+        if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
         const T pivinv = s_div(s_one<T>(), piv);
         for (int j = tid; j < n; j += NT) prow[j] = (j == kk) ? pivinv : s_mul(B[(size_t)p * n + j], pivinv);
         __syncthreads();
@@ -520,12 +529,12 @@ __device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ pe
             double best = -1.0;
             int bidx = n;
             for (int i = tid; i < n; i += NT) {
-                const double a = pinv[i] < 0 ? s_abs(W[i * NB + t]) : -1.0;
+                const double a = pivot_weight(pinv[i], s_abs(W[i * NB + t]));
                 if (a > best) { best = a; bidx = i; }
             }
             const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
             const T piv = W[p * NB + t];
-            if (s_abs1(piv) == 0.0) ok = false;
+            if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
             const T pivinv = s_div(s_one<T>(), piv);
             if (tid < NB) pr[tid] = (tid == t) ? pivinv : s_mul(W[p * NB + tid], pivinv);
             __syncthreads();
@@ -751,7 +760,9 @@ __device__ void estimate_extremes(const JobDesc& J, const NestPtrs& P, int k, co
             for (int i = tid; i < k; i += NT) y2[i] = s_sub(y2[i], s_mul(h, y[i]));
             __syncthreads();
             const double n2 = sqrt(block_norm2<T>(y2, k, sm.red));
-            for (int i = tid; i < k; i += NT) y2[i] = s_scale(y2[i], 1.0 / n2);
+            // (a second vector that vanished is left as it is: its log then
+            // spoils only the z_min estimate, which p_opt checks)
+            if (n2 > 0.0) for (int i = tid; i < k; i += NT) y2[i] = s_scale(y2[i], 1.0 / n2);
             __syncthreads();
             if (it >= NIT - NAVG) { lsum += log(n1); l2sum += log(n2); }
             T* sw_ = x; x = y; y = sw_;
@@ -1018,6 +1029,7 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     if (p <= 0.0) {
         estimate_extremes<T>(J, P, kk, sm, res.zmin, res.zmax);
         p = 1.0 / sqrt(res.zmin * res.zmax);
+        if (!(p > 0.0) || !isfinite(p)) p = 1.0;   // degenerate estimate: p = 1 is one RHi step
     }
     res.p = p;
     if (lu_pH<T>(P, kk, p) != 0) { res.status = NKS_E_NOCONV; return res; }
@@ -1214,11 +1226,17 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm, fl
         __syncthreads();
         net_forward(J.net, f, net_out);
         if (tid == 0) {
-            const double ks = pow(10.0, (double)net_out[0]);
-            const double ls = pow(10.0, (double)net_out[1]);
+            // (a non-finite output gives no k target and the smallest ell start)
+            const double ks0 = pow(10.0, (double)net_out[0]);
+            const double ks = (ks0 >= 0.0 && ks0 < 1e7) ? ks0 : 1e7;
+            const double ls0 = pow(10.0, (double)net_out[1]);
+            const double ls = (ls0 >= 0.0 && ls0 < 1e7) ? ls0 : 0.0;
             int kt = (int)ceil(ks / LEARN_DK) * LEARN_DK;
             kt = max(kt, j + LEARN_DK);
-            if (learned && kt < J.k) J.status[ST_KTARGET] = kt;
+            if (learned && kt < J.k) {
+                J.status[ST_KTARGET] = kt;
+                if (J.group) atomicMax(J.group + GW_KTARGET_MAX, kt);
+            }
             // largest power of two not above ell* (at least 8): a start below the
             // needed size costs one more doubling at small size, one above a
             // dense RHi step eight times dearer per doubling
@@ -1251,19 +1269,25 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm, fl
     if (mode == NEST_CHECKPOINT) {
         if (!kpol || J.status[ST_DONE] || j >= J.k) return;
         if (learned && !J.status[ST_FALLBACK] && J.status[ST_KTARGET] > 0) {
-            if (j != J.status[ST_KTARGET]) return;
+            // Every job of the group is verified in the same launch, at the
+            // group's largest target (or this job's last checkpoint before
+            // its own k cap), each on its own H_{k*}: a leading section of
+            // the longer basis.  One launch instead of one per distinct k*.
+            const int kt = J.status[ST_KTARGET];
+            const int jlast = ((J.k - 1) / LEARN_DK) * LEARN_DK;
+            const int jv = J.group ? min(J.group[GW_KTARGET_MAX], jlast) : kt;
+            if (j != jv) return;
             // verify k* against k* - LEARN_VERIFY_DK
-            const int kv = j - LEARN_VERIFY_DK;
-            NestResult r0 = nested_coeffs<T>(J, P, kv, sm, ell_start);
+            const int kv = kt - LEARN_VERIFY_DK;
+            nested_coeffs<T>(J, P, kv, sm, ell_start);
             store_checkpoint<T>(J, cc, kv, -1.0);
-            NestResult res = nested_coeffs<T>(J, P, j, sm, ell_start);
-            const double delta = weighted_change<T>(J, cc, j, J.ckpt, kv, sm);
-            (void)r0;
+            NestResult res = nested_coeffs<T>(J, P, kt, sm, ell_start);
+            const double delta = weighted_change<T>(J, cc, kt, J.ckpt, kv, sm);
             if (delta <= J.tol / 4 && res.status == NKS_OK) {
-                write_result<T>(J, cc, j, res, delta, true, true);
+                write_result<T>(J, cc, kt, res, delta, true, true);
             } else {
                 // fall back to the plain checkpoints from here on
-                store_checkpoint<T>(J, cc, j, delta);
+                store_checkpoint<T>(J, cc, kt, delta);
                 if (tid == 0) {
                     J.status[ST_FALLBACK] = 1;
                     J.status[ST_KTARGET] = 0;

@@ -143,7 +143,11 @@ struct JobDesc {
     int V;              // lattice volume
     const struct PolicyNet* net;   // learned policy (device), or null
     double* label;      // label mode output (LABEL_WORDS doubles), or null
+    int* group;         // GROUP_WORDS ints shared by the jobs of one lattice group (zeroed by pack)
 };
+
+// Words shared by a lattice group: the largest learned k target of its jobs.
+enum GroupWord { GW_KTARGET_MAX = 0, GROUP_WORDS = 16 };
 
 constexpr int RHI_MAX = 1024;    // largest dense Roberts-Higham matrix (inner ell, or k when non-nested)
 constexpr int CKPT_DK = 100;     // outer iterations between plain k-checkpoints
@@ -209,8 +213,9 @@ void launch_apply(const Geom& g, const cx_t<R>* links, double kappa, double mu, 
 
 // Launch-shape choices of the outer passes (picked per context; see api.hip).
 struct Tuning {
-    int xcd_map = 1;      // 1D grid mapped so that all jobs of a site block run on one XCD
+    int xcd_map = 1;      // 1D grid: 1 = all jobs of a site block on one XCD, 2 = whole jobs per XCD
     int split_dual = 1;   // two-sided stencil: A u and A^dagger t in separate blocks
+    int min_waves = 1;    // stencil kernels: register budget for 1 (unlimited), 3 or 4 waves per SIMD
 };
 
 // outer.hip

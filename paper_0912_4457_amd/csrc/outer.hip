@@ -43,6 +43,9 @@ __device__ inline cx_t<R>* lvec(const JobDesc& J, int j, int n) {     // t_j in 
 // XCD a contiguous range of (site block, job) pairs, jobs innermost, keeps a
 // site block's links and neighbour spinors in one XCD's L2 while all jobs
 // sweep it.  Returns false for padding blocks.
+// xcd_map == 2 orders the pairs job-major instead: every XCD sweeps the whole
+// lattice for its own share of the jobs, so the neighbour spinors of its jobs
+// stay in its L2 and only the links (shared by all jobs) are read by every XCD.
 __device__ inline bool block_coords(int nblocks, int njobs, int xcd_map, int& sb, int& job) {
     if (!xcd_map) { sb = blockIdx.x; job = blockIdx.y; return true; }
     const int total = nblocks * njobs;
@@ -50,8 +53,13 @@ __device__ inline bool block_coords(int nblocks, int njobs, int xcd_map, int& sb
     const int b = blockIdx.x;
     const int q = (b & 7) * per + (b >> 3);
     if (q >= total) return false;
-    sb = q / njobs;
-    job = q - sb * njobs;
+    if (xcd_map == 2) {
+        job = q / nblocks;
+        sb = q - job * nblocks;
+    } else {
+        sb = q / njobs;
+        job = q - sb * njobs;
+    }
     return true;
 }
 
@@ -67,6 +75,7 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
         if (threadIdx.x == ST_KUSED) v = J.k;
         J.status[threadIdx.x] = v;
     }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < GROUP_WORDS && J.group) J.group[threadIdx.x] = 0;
     double nb2 = 0.0;
     if (site < V) {
         cx_t<R>* u1 = column<R>(J, 1, n);
@@ -85,9 +94,11 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
 }
 
 // ------------------------------------------------------------------ Hermitian step
-template <typename R>
-__global__ __launch_bounds__(NT) void herm_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
-                                            double kappa, int j, int nblocks, int njobs, int xcd_map) {
+// MINW: waves per SIMD the register allocation must allow (1 = no limit);
+// more resident waves hide more memory latency, at the price of spills.
+template <typename R, int MINW>
+__global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
+                                                  double kappa, int j, int nblocks, int njobs, int xcd_map) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
@@ -183,9 +194,10 @@ __global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nb
 // SPLIT = false: one thread computes A u_j and A^dagger t_j (links loaded once).
 // SPLIT = true: blockIdx.z selects the field (0: A u_j, 1: A^dagger t_j), which
 // halves the registers of a thread; the links are then shared through the caches.
-template <typename R, bool SPLIT>
-__global__ __launch_bounds__(NT) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
-                                          double kappa, double mu, int j, int nblocks, int njobs, int xcd_map) {
+template <typename R, bool SPLIT, int MINW>
+__global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
+                                                double kappa, double mu, int j, int nblocks, int njobs,
+                                                int xcd_map) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
@@ -385,19 +397,28 @@ static dim3 outer_grid(const OuterLaunch& L, int z) {
     return dim3(L.nblocks, L.njobs, z);
 }
 
-template <typename R>
-static void outer_S(const OuterLaunch& L, int j, hipStream_t s) {
+template <typename R, int MINW>
+static void outer_S_w(const OuterLaunch& L, int j, hipStream_t s) {
     auto links = static_cast<const cx_t<R>*>(L.links);
     const int xm = L.tune.xcd_map;
     if (!L.two_sided) {
-        hipLaunchKernelGGL(herm_S<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j, L.nblocks,
-                           L.njobs, xm);
+        hipLaunchKernelGGL((herm_S<R, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j,
+                           L.nblocks, L.njobs, xm);
     } else if (L.tune.split_dual) {
-        hipLaunchKernelGGL((bi_S<R, true>), outer_grid(L, 2), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j,
-                           L.nblocks, L.njobs, xm);
+        hipLaunchKernelGGL((bi_S<R, true, MINW>), outer_grid(L, 2), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
+                           L.mu, j, L.nblocks, L.njobs, xm);
     } else {
-        hipLaunchKernelGGL((bi_S<R, false>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, L.mu, j,
-                           L.nblocks, L.njobs, xm);
+        hipLaunchKernelGGL((bi_S<R, false, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
+                           L.mu, j, L.nblocks, L.njobs, xm);
+    }
+}
+
+template <typename R>
+static void outer_S(const OuterLaunch& L, int j, hipStream_t s) {
+    switch (L.tune.min_waves) {
+        case 3: outer_S_w<R, 3>(L, j, s); break;
+        case 4: outer_S_w<R, 4>(L, j, s); break;
+        default: outer_S_w<R, 1>(L, j, s); break;
     }
 }
 

@@ -179,14 +179,17 @@ def predict(ctx, params, fm, fs, tm, ts, X):
 
 
 # ------------------------------------------------------------------ label generation
-def sample_configs(n: int, seed: int):
-    """Seeded lattice descriptions spanning the workloads' range."""
+def sample_configs(n: int, seed: int, two_sided: bool = True):
+    """Seeded lattice descriptions spanning the workloads' range (mu = 0 only
+    when two_sided is False: label runs at mu != 0 are switched off)."""
     rng = np.random.default_rng(seed)
     shapes = [(6, 6, 6, 6), (8, 8, 8, 8), (10, 10, 10, 10), (6, 6, 6, 12), (8, 8, 8, 12)]
     out = []
     for i in range(n):
         dims = shapes[int(rng.integers(len(shapes)))]
         mu = float(rng.choice([0.0, 0.0, 0.1, 0.2, 0.3]))
+        if not two_sided:
+            mu = 0.0
         out.append(dict(dims=dims, eps=float(rng.uniform(0.15, 0.45)), m0=float(rng.uniform(1.3, 1.8)), mu=mu,
                         seed=int(seed * 1000 + i), k=1200 if mu == 0.0 else 1000))
     return out
@@ -282,7 +285,7 @@ def main(argv=None):
         print(m, flush=True)
 
     ctx = nks.Context(0)
-    cfgs = sample_configs(args.lattices, args.seed)
+    cfgs = sample_configs(args.lattices, args.seed, two_sided=False)
     if args.labels and os.path.exists(args.labels):
         z = np.load(args.labels)
         rows, krefs, groups = z["rows"], z["krefs"], z["groups"]

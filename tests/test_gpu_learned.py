@@ -85,6 +85,13 @@ def test_prediction_beyond_k_cap_behaves_as_doubling():
     nks.policy_load(ctx(), constant_net(300, 64))
 
 
+def test_two_sided_label_runs_are_refused():
+    import paper_0912_4457_amd as nks
+    with pytest.raises(nks.NKSError):
+        nks.policy_label([dict(lat=lattice(DIMS, EPS, SEED, 0.3), b=I.gaussian_source(DIMS, SRC).ravel(), k=200,
+                               ell=64, tol=1e-8)])
+
+
 def test_learned_policy_needs_a_network():
     import paper_0912_4457_amd as nks
     c = nks.Context(0)
@@ -115,7 +122,12 @@ def _ritz(mu, k):
     return krylov.two_sided_lanczos(op.matvec, op.rmatvec, b, k)
 
 
-@pytest.mark.parametrize("mu", [0.0, 0.3])
+TWO_SIDED_LABEL_OFF = pytest.mark.skip(
+    reason="two-sided label runs faulted the GPU (memory aperture violation in the label kernel, "
+           "4^4 mu=0.3 k=400); switched off in nks_policy_label until the cause is shown")
+
+
+@pytest.mark.parametrize("mu", [0.0, pytest.param(0.3, marks=TWO_SIDED_LABEL_OFF)])
 def test_label_errors_match_oracle(mu):
     from oracle import policy
     from paper_0912_4457_amd import policy as P
@@ -146,7 +158,7 @@ def test_label_errors_match_oracle(mu):
     assert fin.size >= 1 and np.all(fin >= 0)
 
 
-@pytest.mark.parametrize("mu", [0.0, 0.3])
+@pytest.mark.parametrize("mu", [0.0, pytest.param(0.3, marks=TWO_SIDED_LABEL_OFF)])
 def test_label_features_match_oracle(mu):
     from paper_0912_4457_amd import policy as P
     f = _labels(mu)[:P.NFEAT]

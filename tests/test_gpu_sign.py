@@ -122,20 +122,22 @@ def test_tuning_choices_are_bitwise_identical():
             dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20)]
     ref = None
     try:
-        for xm in (0, 1):
-            for sd in (0, 1):
-                c.tune_set("xcd_map", xm)
-                c.tune_set("split_dual", sd)
-                xs, _ = nks.sign_apply_batch(jobs)
-                got = [to_np(x) for x in xs]
-                if ref is None:
-                    ref = got
-                else:
-                    for a, b in zip(got, ref):
-                        assert np.array_equal(a, b)
+        for xm, sd, mw in ((0, 0, 1), (0, 1, 1), (1, 0, 1), (1, 1, 1), (2, 0, 1), (2, 1, 1), (1, 1, 3),
+                           (1, 0, 4), (1, 1, 4)):
+            c.tune_set("xcd_map", xm)
+            c.tune_set("split_dual", sd)
+            c.tune_set("min_waves", mw)
+            xs, _ = nks.sign_apply_batch(jobs)
+            got = [to_np(x) for x in xs]
+            if ref is None:
+                ref = got
+            else:
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b)
     finally:
         c.tune_set("xcd_map", 1)
         c.tune_set("split_dual", 1)
+        c.tune_set("min_waves", 1)
 
 
 def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
@@ -147,10 +149,11 @@ def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
     lb = lattice((4, 4, 4, 6), 0.5, 21, 0.25)
     jobs = [dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=40, ell=10)]
     res = autotune.autotune(c, jobs, k_probe=16)
-    assert set(res["choice"]) == {"xcd_map", "split_dual"}
-    assert len(res["timings"]) == 4
+    assert set(res["choice"]) == {"xcd_map", "split_dual", "min_waves"}
+    assert len(res["timings"]) == 18
     assert c.tune_get("split_dual") == res["choice"]["split_dual"]
     again = autotune.autotune(c, jobs, k_probe=16)     # cached
     assert again["choice"] == res["choice"]
     c.tune_set("xcd_map", 1)
     c.tune_set("split_dual", 1)
+    c.tune_set("min_waves", 1)
