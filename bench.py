@@ -36,6 +36,7 @@ DIMS = (10, 10, 10, 10)
 EPS, LINK_SEED, M0 = 0.35, 10401, 1.6
 MUS = (0.0, 0.2)
 K, ELL = 500, 64
+SERIAL_GROUPS = False    # --serial-groups
 KERNEL_SOURCES = ("paper_0912_4457_amd/csrc/wilson.h", "paper_0912_4457_amd/csrc/outer.hip")
 
 
@@ -121,8 +122,8 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
     for _ in range(warmup):
         xs, sts = nks.sign_apply_batch(jobs, stats=False)
     torch.cuda.synchronize()
-    if profile:
-        ctx.profile(True)
+    # timed region: the library's default path (graph replay, lattice groups
+    # on concurrent streams)
     t0 = time.perf_counter()
     for _ in range(steps):
         xs, _ = nks.sign_apply_batch(jobs, stats=False)
@@ -130,10 +131,19 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
     dt = time.perf_counter() - t0
     prof = {}
     if profile:
+        # per-kernel launch durations: the same steps again with the groups one
+        # after another (overlapping groups would stretch every launch's span)
+        # and HIP events on one launch in eight of each kernel class
+        ctx.tune_set("concurrent_groups", 0)
+        ctx.profile(True)
+        for _ in range(steps):
+            nks.sign_apply_batch(jobs, stats=False)
+        torch.cuda.synchronize()
         for kc in ("stencil", "recurrence", "nested", "lift"):
             n, ms, by = ctx.profile_read(kc)
             prof[kc] = dict(launches=n, avg_ms=(ms / n if n else None), alg_bytes=(by / n if n else None))
         ctx.profile(False)
+        ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
     xs, sts = nks.sign_apply_batch(jobs, stats=True)   # one more call for the per-job report
     torch.cuda.synchronize()
     errs = errors_vs_golden(jobs, xs, gold)
@@ -288,6 +298,9 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the policy and uneven-batch sections")
+    ap.add_argument("--serial-groups", action="store_true",
+                    help="run the lattice groups one after another everywhere (for kernel traces whose "
+                         "per-launch durations must not include overlap)")
     ap.add_argument("--probe", action="store_true",
                     help="short run of the main path only (for hardware-counter passes)")
     a = ap.parse_args()
@@ -305,6 +318,10 @@ def main():
         return
     import paper_0912_4457_amd as nks
     ctx = nks.Context(0)
+    if a.serial_groups:
+        global SERIAL_GROUPS
+        SERIAL_GROUPS = True
+        ctx.tune_set("concurrent_groups", 0)
     gold = golden_samples()
 
     if a.probe:
@@ -325,6 +342,9 @@ def main():
     lats_g, jobs_g = make_jobs(nks, torch, ctx, a.precision)
     graph_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
     eager_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=False)
+    ctx.tune_set("concurrent_groups", 0)
+    serial_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
+    ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
     for lat in lats_g:
         lat.close()
     paths = uneven = None
@@ -368,7 +388,9 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": st["alg_bytes"], "avg_launch_ms": st["avg_ms"],
-                     "timed_launches": st["launches"]},
+                     "timed_launches": st["launches"],
+                     "launch_timing": "HIP events on the launch stream, one launch in eight, over a second pass "
+                                      "of the timed steps with the lattice groups one after another"},
         "cpu_baseline": cpu,
         "kernels": main_run["prof"],
         "max_rel_err_vs_oracle": (max(main_run["errs"]) if main_run["errs"] else None),
@@ -380,7 +402,8 @@ def main():
                        "value": other_run["napps"] * other_run["steps"] / other_run["seconds"],
                        "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None)},
         "graph_replay": {"value": main_run["napps"] * a.steps / graph_dt,
-                         "eager_value": main_run["napps"] * a.steps / eager_dt},
+                         "eager_value": main_run["napps"] * a.steps / eager_dt,
+                         "groups_one_after_another_value": main_run["napps"] * a.steps / serial_dt},
         "policy_paths": paths,
         "uneven_batch": uneven,
         "stencil_large": large,

@@ -267,6 +267,9 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  *   "min_waves"  1, 3 or 4: register budget of the stencil kernels for that
  *                many resident waves per SIMD (1 = unlimited; more waves
  *                hide more latency, fewer registers may spill)
+ *   "concurrent_groups" 1: the lattice groups of a batched call run on
+ *                separate streams forked from (and joined back to) the call's
+ *                stream; 0: one after another on the call's stream
  *   "graph"      1: capture and replay batched calls as HIP graphs (see
  *                nks_sign_apply_batch); 0: launch eagerly.
  * Read-only counters: "graph_captures", "graph_replays".

@@ -35,6 +35,10 @@ struct nks_ctx {
     // graph mode: captured launch sequences keyed by the job table they were captured for
     int graph = 1;
     hipStream_t cap = nullptr;    // private stream the sequences are captured on
+    // side streams and fork/join events for lattice groups run concurrently
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
     struct Graph {
         std::vector<char> key;
         hipGraphExec_t exec = nullptr;
@@ -303,11 +307,53 @@ enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1, PH_LABEL = 2 };
 
 // Enqueue the whole method for all jobs; the job table must already be on the
 // device at the start of ws.  Events (when timed) mark phase ends.
-int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s,
+// Streams for the lattice groups: group 0 on the call's stream, the others
+// on side streams that fork from it and join it again (all at the default
+// priority).  With concurrency off every group uses the call's stream.
+int ensure_side_streams(nks_ctx* ctx, size_t ngroups) {
+    if (!ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    while (ctx->side.size() + 1 < ngroups) {
+        hipStream_t st;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->side.push_back(st);
+        hipEvent_t e;
+        HIP_TRY(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->join.push_back(e);
+    }
+    return NKS_OK;
+}
+
+int fork_groups(nks_ctx* ctx, size_t ngroups, hipStream_t s) {
+    if (!ctx->tune.concurrent || ngroups < 2) return NKS_OK;
+    int rc = ensure_side_streams(ctx, ngroups);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipEventRecord(ctx->fork, s));
+    for (size_t g = 1; g < ngroups; ++g) HIP_TRY(ctx, hipStreamWaitEvent(ctx->side[g - 1], ctx->fork, 0));
+    return NKS_OK;
+}
+
+int join_groups(nks_ctx* ctx, size_t ngroups, hipStream_t s) {
+    if (!ctx->tune.concurrent || ngroups < 2) return NKS_OK;
+    for (size_t g = 1; g < ngroups; ++g) {
+        HIP_TRY(ctx, hipEventRecord(ctx->join[g - 1], ctx->side[g - 1]));
+        HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->join[g - 1], 0));
+    }
+    return NKS_OK;
+}
+
+hipStream_t group_stream(const nks_ctx* ctx, size_t gi, size_t ngroups, hipStream_t s) {
+    return (ctx->tune.concurrent && ngroups >= 2 && gi > 0) ? ctx->side[gi - 1] : s;
+}
+
+int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s0,
                     bool timed, int phase) {
     JobDesc* table = reinterpret_cast<JobDesc*>(ws);
-    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s));
-    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    const size_t ng = P.groups.size();
+    if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s0));
+    int frc = fork_groups(ctx, ng, s0);
+    if (frc) return frc;
+    for (size_t gi = 0; gi < ng; ++gi) {
+        hipStream_t s = group_stream(ctx, gi, ng, s0);
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const int start = P.groups[gi].first;
         bool kpol = false, learned = false, klearned = false;
@@ -332,6 +378,9 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
             }
         }
     }
+    frc = join_groups(ctx, ng, s0);
+    if (frc) return frc;
+    hipStream_t s = s0;
     launch_finalize(table, (int)descs.size(), s);
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[1], s));
@@ -351,15 +400,20 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
     }
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
-    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    frc = fork_groups(ctx, ng, s0);
+    if (frc) return frc;
+    for (size_t gi = 0; gi < ng; ++gi) {
+        hipStream_t sl = group_stream(ctx, gi, ng, s0);
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const long long c = ctx->prof_count[NKS_K_LIFT];
         ctx->prof_count[NKS_K_LIFT] = 0;
-        int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, s);
+        int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, sl);
         ctx->prof_count[NKS_K_LIFT] = c + 1;
-        launch_lift(L, s);
-        prof_end(ctx, r, s);
+        launch_lift(L, sl);
+        prof_end(ctx, r, sl);
     }
+    frc = join_groups(ctx, ng, s0);
+    if (frc) return frc;
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[3], s));
     return NKS_OK;
@@ -508,6 +562,9 @@ void nks_destroy(nks_ctx* ctx) {
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->net) (void)hipFree(ctx->net);
     for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& st : ctx->side) (void)hipStreamDestroy(st);
+    for (auto& e : ctx->join) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
@@ -844,6 +901,7 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
         if (value < 0 || value > 2) return fail(ctx, NKS_E_INVALID, "xcd_map takes 0, 1 or 2");
         ctx->tune.xcd_map = value;
     } else if (k == "split_dual") ctx->tune.split_dual = value != 0;
+    else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;
     else if (k == "min_waves") {
         if (value != 1 && value != 3 && value != 4) return fail(ctx, NKS_E_INVALID, "min_waves takes 1, 3 or 4");
         ctx->tune.min_waves = value;
@@ -858,6 +916,7 @@ int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
     if (k == "xcd_map") *value = ctx->tune.xcd_map;
     else if (k == "split_dual") *value = ctx->tune.split_dual;
     else if (k == "min_waves") *value = ctx->tune.min_waves;
+    else if (k == "concurrent_groups") *value = ctx->tune.concurrent;
     else if (k == "graph") *value = ctx->graph;
     else if (k == "graph_captures") *value = (int)ctx->graph_captures;
     else if (k == "graph_replays") *value = (int)ctx->graph_replays;

@@ -216,6 +216,7 @@ struct Tuning {
     int xcd_map = 1;      // 1D grid: 1 = all jobs of a site block on one XCD, 2 = whole jobs per XCD
     int split_dual = 1;   // two-sided stencil: A u and A^dagger t in separate blocks
     int min_waves = 1;    // stencil kernels: register budget for 1 (unlimited), 3 or 4 waves per SIMD
+    int concurrent = 1;   // lattice groups of a batch on separate streams (1) or one after another (0)
 };
 
 // outer.hip

@@ -122,11 +122,12 @@ def test_tuning_choices_are_bitwise_identical():
             dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20)]
     ref = None
     try:
-        for xm, sd, mw in ((0, 0, 1), (0, 1, 1), (1, 0, 1), (1, 1, 1), (2, 0, 1), (2, 1, 1), (1, 1, 3),
-                           (1, 0, 4), (1, 1, 4)):
+        for xm, sd, mw, cg in ((0, 0, 1, 1), (0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 1, 1), (2, 0, 1, 1),
+                               (2, 1, 1, 1), (1, 1, 3, 1), (1, 0, 4, 1), (1, 1, 4, 1), (1, 1, 1, 0)):
             c.tune_set("xcd_map", xm)
             c.tune_set("split_dual", sd)
             c.tune_set("min_waves", mw)
+            c.tune_set("concurrent_groups", cg)
             xs, _ = nks.sign_apply_batch(jobs)
             got = [to_np(x) for x in xs]
             if ref is None:
@@ -138,6 +139,7 @@ def test_tuning_choices_are_bitwise_identical():
         c.tune_set("xcd_map", 1)
         c.tune_set("split_dual", 1)
         c.tune_set("min_waves", 1)
+        c.tune_set("concurrent_groups", 1)
 
 
 def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
