@@ -342,6 +342,9 @@ def main():
     lats_g, jobs_g = make_jobs(nks, torch, ctx, a.precision)
     graph_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
     eager_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=False)
+    ctx.tune_set("pipeline_groups", 1)
+    pipe_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
+    ctx.tune_set("pipeline_groups", 0)
     ctx.tune_set("concurrent_groups", 0)
     serial_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)
     ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
@@ -403,7 +406,8 @@ def main():
                        "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None)},
         "graph_replay": {"value": main_run["napps"] * a.steps / graph_dt,
                          "eager_value": main_run["napps"] * a.steps / eager_dt,
-                         "groups_one_after_another_value": main_run["napps"] * a.steps / serial_dt},
+                         "groups_one_after_another_value": main_run["napps"] * a.steps / serial_dt,
+                         "pipelined_groups_value": main_run["napps"] * a.steps / pipe_dt},
         "policy_paths": paths,
         "uneven_batch": uneven,
         "stencil_large": large,

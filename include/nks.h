@@ -270,6 +270,11 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  *   "concurrent_groups" 1: the lattice groups of a batched call run on
  *                separate streams forked from (and joined back to) the call's
  *                stream; 0: one after another on the call's stream
+ *   "pipeline_groups" 1 (with concurrent groups, calls without stats): each
+ *                group's nested step and lift follow its own outer loop on
+ *                its stream; 0 (default): one nested launch for all jobs
+ *                after the join (measured 1 % faster at 10^4: the lift of one
+ *                group competes with the other group's stencil for HBM)
  *   "graph"      1: capture and replay batched calls as HIP graphs (see
  *                nks_sign_apply_batch); 0: launch eagerly.
  * Read-only counters: "graph_captures", "graph_replays".

@@ -349,6 +349,10 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
                     bool timed, int phase) {
     JobDesc* table = reinterpret_cast<JobDesc*>(ws);
     const size_t ng = P.groups.size();
+    // With concurrent groups (and no per-phase timing) each group also runs its
+    // own nested step and lift right after its outer loop, so they overlap the
+    // outer loops of slower groups.
+    const bool pipe = !timed && phase == PH_ALL && ctx->tune.concurrent && ctx->tune.pipeline && ng >= 2;
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s0));
     int frc = fork_groups(ctx, ng, s0);
     if (frc) return frc;
@@ -377,9 +381,26 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
                     launch_checkpoint(L.jobs, L.njobs, j, s);
             }
         }
+        if (pipe) {
+            launch_finalize(L.jobs, L.njobs, s);
+            const long long c = ctx->prof_count[NKS_K_NESTED];
+            ctx->prof_count[NKS_K_NESTED] = 0;
+            int r = prof_begin(ctx, NKS_K_NESTED, 0.0, s);
+            ctx->prof_count[NKS_K_NESTED] = c + 1;
+            launch_nested(L.jobs, L.njobs, s);
+            prof_end(ctx, r, s);
+            const long long c2 = ctx->prof_count[NKS_K_LIFT];
+            ctx->prof_count[NKS_K_LIFT] = 0;
+            r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, start) : 0.0, s);
+            ctx->prof_count[NKS_K_LIFT] = c2 + 1;
+            launch_lift(L, s);
+            prof_end(ctx, r, s);
+        }
     }
     frc = join_groups(ctx, ng, s0);
     if (frc) return frc;
+    HIP_TRY(ctx, hipGetLastError());
+    if (pipe) return NKS_OK;
     hipStream_t s = s0;
     launch_finalize(table, (int)descs.size(), s);
     HIP_TRY(ctx, hipGetLastError());
@@ -902,6 +923,7 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
         ctx->tune.xcd_map = value;
     } else if (k == "split_dual") ctx->tune.split_dual = value != 0;
     else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;
+    else if (k == "pipeline_groups") ctx->tune.pipeline = value != 0;
     else if (k == "min_waves") {
         if (value != 1 && value != 3 && value != 4) return fail(ctx, NKS_E_INVALID, "min_waves takes 1, 3 or 4");
         ctx->tune.min_waves = value;
@@ -917,6 +939,7 @@ int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
     else if (k == "split_dual") *value = ctx->tune.split_dual;
     else if (k == "min_waves") *value = ctx->tune.min_waves;
     else if (k == "concurrent_groups") *value = ctx->tune.concurrent;
+    else if (k == "pipeline_groups") *value = ctx->tune.pipeline;
     else if (k == "graph") *value = ctx->graph;
     else if (k == "graph_captures") *value = (int)ctx->graph_captures;
     else if (k == "graph_replays") *value = (int)ctx->graph_replays;

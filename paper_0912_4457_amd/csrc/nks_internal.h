@@ -217,6 +217,7 @@ struct Tuning {
     int split_dual = 1;   // two-sided stencil: A u and A^dagger t in separate blocks
     int min_waves = 1;    // stencil kernels: register budget for 1 (unlimited), 3 or 4 waves per SIMD
     int concurrent = 1;   // lattice groups of a batch on separate streams (1) or one after another (0)
+    int pipeline = 0;     // with concurrent groups: each group's nested step and lift follow its own outer loop
 };
 
 // outer.hip
