@@ -98,6 +98,8 @@ def make_jobs(nks, torch, ctx, precision, **policy):
 
 
 def errors_vs_golden(jobs, xs, gold):
+    """Relative error on the sampled entries; for overlap jobs the reference is
+    b + gamma5 sgn(A) b on the same entries."""
     import numpy as np
     if gold is None:
         return None
@@ -107,6 +109,9 @@ def errors_vs_golden(jobs, xs, gold):
                     if c["mu"] == j["mu"] and c["spin"] == j["spin"] and c["colour"] == j["colour"])
         idx = np.asarray(case["idx"])
         ref = np.asarray(case["re"]) + 1j * np.asarray(case["im"])
+        if j.get("overlap"):
+            g5 = np.where((idx % 12) >= 6, -1.0, 1.0)
+            ref = j["b"].cpu().numpy()[idx] + g5 * ref
         got = x.cpu().numpy()[idx]
         errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
     return errs
@@ -190,6 +195,19 @@ def policy_paths(nks, torch, ctx, gold, steps):
         for lat in lats:
             lat.close()
     return out
+
+
+def overlap_path(nks, torch, ctx, gold, steps):
+    """The overlap operator D_ov b = b + gamma5 sgn(A) b on the same 24 jobs."""
+    lats, jobs = make_jobs(nks, torch, ctx, "fp64", overlap=True)
+    dt = time_calls(nks, torch, jobs, steps, 1)
+    xs, sts = nks.sign_apply_batch(jobs, stats=True)
+    torch.cuda.synchronize()
+    errs = errors_vs_golden(jobs, xs, gold)
+    for lat in lats:
+        lat.close()
+    return {"value": len(jobs) * steps / dt, "unit": "overlap applications/s",
+            "max_rel_err_vs_oracle": max(errs) if errs else None}
 
 
 def uneven_batch(nks, torch, ctx, steps):
@@ -350,10 +368,12 @@ def main():
     ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
     for lat in lats_g:
         lat.close()
-    paths = uneven = None
+    paths = uneven = overlap_res = None
     if not a.no_extra:
         log("[bench] policy paths")
         paths = policy_paths(nks, torch, ctx, gold, max(2, a.steps // 2))
+        log("[bench] overlap operator")
+        overlap_res = overlap_path(nks, torch, ctx, gold, a.steps)
         log("[bench] uneven batch")
         uneven = uneven_batch(nks, torch, ctx, 2)
     large = None
@@ -409,6 +429,7 @@ def main():
                          "groups_one_after_another_value": main_run["napps"] * a.steps / serial_dt,
                          "pipelined_groups_value": main_run["napps"] * a.steps / pipe_dt},
         "policy_paths": paths,
+        "overlap": overlap_res,
         "uneven_batch": uneven,
         "stencil_large": large,
         "tuning": main_run["tuned"],

@@ -93,8 +93,14 @@ typedef struct nks_opts {
     int ell_policy;       /* enum nks_policy */
     int max_rhi_iter;     /* Roberts-Higham iteration cap (default 50) */
     double rhi_tol;       /* relative Frobenius change that ends RHi (default 1e-14) */
-    unsigned flags;       /* reserved, 0 */
+    unsigned flags;       /* NKS_FLAG_* bits; others give NKS_E_INVALID */
 } nks_opts;
+
+/* flags: return the overlap operator D_ov(mu) b = b + gamma5 sgn(A) b
+ * (Sec. 2, Eq. Dovmu; A = gamma5 D_w(mu), gamma5 = diag(1, 1, -1, -1) in
+ * spin) instead of sgn(A) b.  The identity and gamma5 terms are added by
+ * the lift kernel; everything else is the sign application. */
+#define NKS_FLAG_OVERLAP 1u
 
 /* Per-result report (filled after the stream completes). */
 typedef struct nks_stats {

@@ -23,6 +23,7 @@ __all__ = [
     "FP64", "MIXED", "POLICY_FIXED", "POLICY_DOUBLING", "POLICY_LEARNED",
     "NKSError", "lib", "Context", "Lattice", "apply_op", "sign_apply", "sign_apply_batch",
     "outer_basis", "nested_step", "workspace_size", "LIB_PATH", "policy_load", "policy_label", "load_policy",
+    "overlap_apply",
     "mlp_forward", "mlp_backward", "mlp_adam_step",
 ]
 
@@ -132,8 +133,11 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+FLAG_OVERLAP = 1
+
+
 def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50, rhi_tol=1e-14,
-              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED) -> Opts:
+              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False) -> Opts:
     o = Opts()
     lib().nks_opts_default(ctypes.byref(o))
     o.k, o.ell, o.tol = int(k), int(ell), float(tol)
@@ -141,6 +145,7 @@ def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50
     o.p = 0.0 if p is None else float(p)
     o.max_rhi_iter, o.rhi_tol = int(max_rhi_iter), float(rhi_tol)
     o.k_policy, o.ell_policy = int(k_policy), int(ell_policy)
+    o.flags = FLAG_OVERLAP if overlap else 0
     return o
 
 
@@ -317,7 +322,8 @@ def sign_apply_batch(jobs, stats: bool = True):
         x = torch.empty_like(b) if x is None else x
         o = make_opts(k=j.get("k", 200), ell=j.get("ell", 50), tol=j.get("tol", 1e-8),
                       precision=j.get("precision", "fp64"), p=j.get("p"),
-                      k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED))
+                      k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED),
+                      overlap=j.get("overlap", False))
         spec.append((lat, b, x, o))
         xs.append(x)
     ctx = spec[0][0].ctx
@@ -329,6 +335,11 @@ def sign_apply_batch(jobs, stats: bool = True):
     ctx.check(lib().nks_sign_apply_batch(ctx.h, len(spec), arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                          _stream(), sts if stats else None))
     return xs, ([s.as_dict() for s in sts] if stats else None)
+
+
+def overlap_apply(lat: Lattice, b, **kw):
+    """D_ov(mu) b = b + gamma5 sgn(gamma5 D_w(mu)) b (Sec. 2); same options as sign_apply."""
+    return sign_apply(lat, b, overlap=True, **kw)
 
 
 def outer_basis(lat: Lattice, b, k: int, precision="fp64"):

@@ -100,6 +100,7 @@ struct JobPlan {
     double tol;
     bool label;         // label run (nks_policy_label): checkpoint buffer + label words
     int group;          // index of its (lattice, precision) group
+    int overlap;        // NKS_FLAG_OVERLAP
     size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
         end;
     bool learned() const { return k_policy == NKS_POLICY_LEARNED || ell_policy == NKS_POLICY_LEARNED; }
@@ -127,6 +128,7 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
         return fail(ctx, NKS_E_INVALID, "unknown policy");
     if ((o->k_policy == NKS_POLICY_LEARNED || o->ell_policy == NKS_POLICY_LEARNED) && !(ctx && ctx->net))
         return fail(ctx, NKS_E_UNSUPPORTED, "learned policy needs a network (nks_policy_load)");
+    if (o->flags & ~(unsigned)NKS_FLAG_OVERLAP) return fail(ctx, NKS_E_INVALID, "unknown flag bits");
     if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
         return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
     return NKS_OK;
@@ -154,6 +156,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.ell_policy = J.opts->ell_policy;
         jp.tol = J.opts->tol;
         jp.label = label;
+        jp.overlap = (J.opts->flags & NKS_FLAG_OVERLAP) ? 1 : 0;
         jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
         if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
             return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
@@ -233,6 +236,7 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.V = jp.lat->g.V;
     d.net = jp.learned() ? ctx->net : nullptr;
     d.group = reinterpret_cast<int*>(ws + P.group_off) + (size_t)GROUP_WORDS * jp.group;
+    d.overlap = jp.overlap;
     return d;
 }
 

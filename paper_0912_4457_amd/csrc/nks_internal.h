@@ -144,6 +144,7 @@ struct JobDesc {
     const struct PolicyNet* net;   // learned policy (device), or null
     double* label;      // label mode output (LABEL_WORDS doubles), or null
     int* group;         // GROUP_WORDS ints shared by the jobs of one lattice group (zeroed by pack)
+    int overlap;        // 1: the lift writes x = b + gamma5 y (overlap operator) instead of y
 };
 
 // Words shared by a lattice group: the largest learned k target of its jobs.

@@ -376,7 +376,13 @@ __global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
         acc1 = cadd(acc1, cmul(J.omega[jj + 1], b));
     }
     if (jj < kused) acc0 = cadd(acc0, cmul(J.omega[jj], to_d2<R>(base[(size_t)jj * n])));
-    J.x[(size_t)12 * s + c] = cadd(acc0, acc1);
+    double2 y = cadd(acc0, acc1);
+    if (J.overlap) {
+        // D_ov(mu) b = b + gamma5 sgn(gamma5 D_w(mu)) b (Sec. 2, Eq. Dovmu); gamma5 = diag(1, 1, -1, -1)
+        const double2 bv = J.b[(size_t)12 * s + c];
+        y = (c < 6) ? cadd(bv, y) : csub(bv, y);
+    }
+    J.x[(size_t)12 * s + c] = y;
 }
 
 }  // namespace
