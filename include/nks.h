@@ -101,6 +101,11 @@ typedef struct nks_opts {
  * spin) instead of sgn(A) b.  The identity and gamma5 terms are added by
  * the lift kernel; everything else is the sign application. */
 #define NKS_FLAG_OVERLAP 1u
+/* flags: deflate with the eigenpairs set on the job's lattice
+ * (nks_lattice_set_deflation; App. C steps 1 and 6): the method runs on
+ * b_m = b - sum_i <l_i, b> r_i and adds sum_i sgn(Re lambda_i) <l_i, b> r_i.
+ * NKS_E_INVALID if the lattice has none. */
+#define NKS_FLAG_DEFLATE 2u
 
 /* Per-result report (filled after the stream completes). */
 typedef struct nks_stats {
@@ -146,6 +151,17 @@ int nks_lattice_create(nks_ctx* ctx, const int32_t dims[4], const void* links_de
  * mu != 0 two-sided Lanczos. */
 int nks_lattice_set_params(nks_lattice* lat, double m0, double mu);
 void nks_lattice_destroy(nks_lattice* lat);
+
+/* Deflation data for later NKS_FLAG_DEFLATE jobs on this lattice (App. C
+ * step 1): m (0..64) eigenpairs of A.  r_dev, l_dev: device, m complex128
+ * vectors each in the caller's layout ([i][12*site + 3*spin + colour]);
+ * l_dev NULL means l_i = r_i (A Hermitian).  The caller normalises them
+ * biorthonormally, l_i^dagger r_j = delta_ij.  lambda_host: 2m doubles,
+ * interleaved complex eigenvalues; Re(lambda_i) = 0 gives NKS_E_INVALID.
+ * The vectors are copied into the lattice (2 m 12 V complex128); m = 0
+ * switches deflation off.  Waits for the device. */
+int nks_lattice_set_deflation(nks_lattice* lat, int m, const void* r_dev, const void* l_dev,
+                              const double* lambda_host);
 
 /* out = A in (dagger = 0) or A^dagger in (dagger = 1), A = gamma5 D_w(mu);
  * A(mu)^dagger = gamma5 D_w(-mu).  precision NKS_MIXED runs the float32

@@ -83,6 +83,7 @@ SIGNATURES = {
     "nks_lattice_create": (_I, [_VP, ctypes.POINTER(ctypes.c_int32), _VP, ctypes.POINTER(_VP)]),
     "nks_lattice_set_params": (_I, [_VP, _D, _D]),
     "nks_lattice_destroy": (None, [_VP]),
+    "nks_lattice_set_deflation": (_I, [_VP, _I, _VP, _VP, _PD]),
     "nks_apply_op": (_I, [_VP, _VP, _VP, _I, _I, _VP]),
     "nks_workspace_size": (_I, [_VP, _I, ctypes.POINTER(Job), ctypes.POINTER(_SZ)]),
     "nks_sign_apply": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
@@ -134,10 +135,11 @@ def _stream():
 
 
 FLAG_OVERLAP = 1
+FLAG_DEFLATE = 2
 
 
 def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50, rhi_tol=1e-14,
-              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False) -> Opts:
+              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False, deflate=False) -> Opts:
     o = Opts()
     lib().nks_opts_default(ctypes.byref(o))
     o.k, o.ell, o.tol = int(k), int(ell), float(tol)
@@ -145,7 +147,7 @@ def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50
     o.p = 0.0 if p is None else float(p)
     o.max_rhi_iter, o.rhi_tol = int(max_rhi_iter), float(rhi_tol)
     o.k_policy, o.ell_policy = int(k_policy), int(ell_policy)
-    o.flags = FLAG_OVERLAP if overlap else 0
+    o.flags = (FLAG_OVERLAP if overlap else 0) | (FLAG_DEFLATE if deflate else 0)
     return o
 
 
@@ -233,6 +235,29 @@ class Lattice:
     def set_params(self, m0: float, mu: float):
         self.ctx.check(lib().nks_lattice_set_params(self.h, float(m0), float(mu)))
         self.m0, self.mu = float(m0), float(mu)
+
+    def set_deflation(self, r, lam, l=None):
+        """Eigenpairs for deflate=True jobs: r (and l, default r) of shape
+        (m, 12*V) complex128, l_i^H r_j = delta_ij; lam the m eigenvalues."""
+        torch = _torch()
+        m = 0 if r is None else len(lam)
+        if m == 0:
+            self.ctx.check(lib().nks_lattice_set_deflation(self.h, 0, None, None, None))
+            self._defl = None
+            return
+        rt = torch.as_tensor(np.ascontiguousarray(r, dtype=np.complex128) if not isinstance(r, torch.Tensor) else r)
+        rt = rt.to(device=f"cuda:{self.ctx.device}", dtype=torch.complex128).contiguous()
+        lt = None
+        if l is not None:
+            lt = torch.as_tensor(np.ascontiguousarray(l, dtype=np.complex128) if not isinstance(l, torch.Tensor) else l)
+            lt = lt.to(device=f"cuda:{self.ctx.device}", dtype=torch.complex128).contiguous()
+        if rt.numel() != m * self.n or (lt is not None and lt.numel() != m * self.n):
+            raise ValueError(f"eigenvectors must hold m * 12 * V = {m * self.n} complex numbers")
+        la = np.ascontiguousarray(np.asarray(lam, dtype=np.complex128)).view(np.float64)
+        self.ctx.check(lib().nks_lattice_set_deflation(self.h, m, ctypes.c_void_p(rt.data_ptr()),
+                                                       ctypes.c_void_p(lt.data_ptr()) if lt is not None else None,
+                                                       la.ctypes.data_as(_PD)))
+        self._defl = (rt, lt)
 
     def close(self):
         if getattr(self, "h", None):
@@ -323,7 +348,7 @@ def sign_apply_batch(jobs, stats: bool = True):
         o = make_opts(k=j.get("k", 200), ell=j.get("ell", 50), tol=j.get("tol", 1e-8),
                       precision=j.get("precision", "fp64"), p=j.get("p"),
                       k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED),
-                      overlap=j.get("overlap", False))
+                      overlap=j.get("overlap", False), deflate=j.get("deflate", False))
         spec.append((lat, b, x, o))
         xs.append(x)
     ctx = spec[0][0].ctx

@@ -56,6 +56,11 @@ struct nks_lattice {
     double2* links64 = nullptr;   // SoA [nu][row][col][site]
     float2* links32 = nullptr;
     double2* tmp = nullptr;       // 2 * 12V complex128 scratch for nks_apply_op
+    // deflation: m eigenpairs, SoA [i][comp][site]
+    int defl_m = 0, defl_cap = 0;
+    double2* defl_r = nullptr;
+    double2* defl_l = nullptr;    // null: left = right (Hermitian)
+    double* defl_sgn = nullptr;
 };
 
 namespace {
@@ -75,6 +80,16 @@ int fail(nks_ctx* ctx, int code, const std::string& msg) {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 constexpr int NONNESTED_MAX = RHI_MAX;   // dense k x k RHi limit of the non-nested mode
+
+// caller layout [i][12*site + comp] -> [i][comp][site]
+__global__ void vecs_to_soa(const double2* __restrict__ in, double2* __restrict__ out, int V, int m) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // e = (i * 12 + comp) * V + site
+    const long long n = 12LL * V;
+    if (e >= n * m) return;
+    const long long i = e / n, r = e - i * n;
+    const int c = (int)(r / V), s = (int)(r - (long long)c * V);
+    out[e] = in[i * n + 12LL * s + c];
+}
 
 __global__ void links_to_soa(const double2* __restrict__ in, double2* __restrict__ o64, float2* __restrict__ o32,
                              int V) {
@@ -101,6 +116,8 @@ struct JobPlan {
     bool label;         // label run (nks_policy_label): checkpoint buffer + label words
     int group;          // index of its (lattice, precision) group
     int overlap;        // NKS_FLAG_OVERLAP
+    int dm;             // deflated eigenpairs (NKS_FLAG_DEFLATE)
+    size_t off_dcoef, off_dpart;
     size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
         end;
     bool learned() const { return k_policy == NKS_POLICY_LEARNED || ell_policy == NKS_POLICY_LEARNED; }
@@ -128,7 +145,7 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
         return fail(ctx, NKS_E_INVALID, "unknown policy");
     if ((o->k_policy == NKS_POLICY_LEARNED || o->ell_policy == NKS_POLICY_LEARNED) && !(ctx && ctx->net))
         return fail(ctx, NKS_E_UNSUPPORTED, "learned policy needs a network (nks_policy_load)");
-    if (o->flags & ~(unsigned)NKS_FLAG_OVERLAP) return fail(ctx, NKS_E_INVALID, "unknown flag bits");
+    if (o->flags & ~(unsigned)(NKS_FLAG_OVERLAP | NKS_FLAG_DEFLATE)) return fail(ctx, NKS_E_INVALID, "unknown flag bits");
     if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
         return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
     return NKS_OK;
@@ -157,6 +174,12 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.tol = J.opts->tol;
         jp.label = label;
         jp.overlap = (J.opts->flags & NKS_FLAG_OVERLAP) ? 1 : 0;
+        jp.dm = 0;
+        if (J.opts->flags & NKS_FLAG_DEFLATE) {
+            if (J.lat->defl_m == 0)
+                return fail(ctx, NKS_E_INVALID, "NKS_FLAG_DEFLATE on a lattice without deflation (nks_lattice_set_deflation)");
+            jp.dm = J.lat->defl_m;
+        }
         jp.lcap = jp.ell >= jp.k ? jp.k : jp.ell;
         if (jp.ell >= jp.k && jp.k > NONNESTED_MAX)
             return fail(ctx, NKS_E_UNSUPPORTED, "non-nested mode (ell >= k) is limited to k <= 1024");
@@ -196,6 +219,8 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         const bool ck = jp.k_policy != NKS_POLICY_FIXED || jp.label;
         jp.off_ckpt = off; off = align_up(off + (ck ? sizeof(double2) * jp.k : 0));
         jp.off_label = off; off = align_up(off + (jp.label ? sizeof(double) * LABEL_WORDS : 0));
+        jp.off_dcoef = off; off = align_up(off + sizeof(double2) * jp.dm);
+        jp.off_dpart = off; off = align_up(off + sizeof(double2) * (size_t)jp.dm * jp.nblocks);
         jp.off_nest = off;
         off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided) * (jp.label ? 1 + LABEL_NK : 1));
         jp.end = off;
@@ -237,6 +262,14 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.net = jp.learned() ? ctx->net : nullptr;
     d.group = reinterpret_cast<int*>(ws + P.group_off) + (size_t)GROUP_WORDS * jp.group;
     d.overlap = jp.overlap;
+    d.dm = jp.dm;
+    if (jp.dm > 0) {
+        d.dr = jp.lat->defl_r;
+        d.dl = jp.lat->defl_l ? jp.lat->defl_l : jp.lat->defl_r;
+        d.dsgn = jp.lat->defl_sgn;
+        d.dcoef = reinterpret_cast<double2*>(ws + jp.off_dcoef);
+        d.dpart = reinterpret_cast<double2*>(ws + jp.off_dpart);
+    }
     return d;
 }
 
@@ -251,7 +284,11 @@ OuterLaunch group_launch(const nks_ctx* ctx, const Plan& P, int gi, JobDesc* tab
     L.jobs = table + start;
     L.njobs = count;
     L.kmax = 0;
-    for (int i = start; i < start + count; ++i) L.kmax = std::max(L.kmax, P.jobs[i].k);
+    L.deflate = 0;
+    for (int i = start; i < start + count; ++i) {
+        L.kmax = std::max(L.kmax, P.jobs[i].k);
+        if (P.jobs[i].dm > 0) L.deflate = 1;
+    }
     L.nblocks = jp.nblocks;
     L.precision = jp.precision;
     L.two_sided = jp.two_sided;
@@ -647,10 +684,55 @@ int nks_lattice_set_params(nks_lattice* lat, double m0, double mu) {
 
 void nks_lattice_destroy(nks_lattice* lat) {
     if (!lat) return;
+    (void)hipFree(lat->defl_r);
+    (void)hipFree(lat->defl_l);
+    (void)hipFree(lat->defl_sgn);
     (void)hipFree(lat->links64);
     (void)hipFree(lat->links32);
     (void)hipFree(lat->tmp);
     delete lat;
+}
+
+int nks_lattice_set_deflation(nks_lattice* lat, int m, const void* r_dev, const void* l_dev,
+                              const double* lambda_host) {
+    if (!lat) return NKS_E_INVALID;
+    nks_ctx* ctx = lat->ctx;
+    if (m < 0 || m > DEFL_MAX) return fail(ctx, NKS_E_INVALID, "deflation takes 0 <= m <= 64 eigenpairs");
+    if (m > 0 && (!r_dev || !lambda_host)) return fail(ctx, NKS_E_INVALID, "NULL eigenvectors or eigenvalues");
+    std::vector<double> sg(m);
+    for (int i = 0; i < m; ++i) {
+        const double re = lambda_host[2 * i];
+        if (!(re == re) || re == 0.0) return fail(ctx, NKS_E_INVALID, "sgn is undefined for Re(lambda) = 0 or NaN");
+        sg[i] = re > 0.0 ? 1.0 : -1.0;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());     // no call in flight may read the old eigenpairs
+    const size_t n = (size_t)12 * lat->g.V;
+    if (m > lat->defl_cap) {
+        (void)hipFree(lat->defl_r);
+        (void)hipFree(lat->defl_l);
+        (void)hipFree(lat->defl_sgn);
+        lat->defl_r = lat->defl_l = nullptr;
+        lat->defl_sgn = nullptr;
+        lat->defl_cap = lat->defl_m = 0;
+        HIP_TRY(ctx, hipMalloc(&lat->defl_r, sizeof(double2) * n * m));
+        HIP_TRY(ctx, hipMalloc(&lat->defl_l, sizeof(double2) * n * m));
+        HIP_TRY(ctx, hipMalloc(&lat->defl_sgn, sizeof(double) * m));
+        lat->defl_cap = m;
+    }
+    if (m > 0) {
+        const long long tot = (long long)n * m;
+        const int nb = (int)((tot + 255) / 256);
+        hipLaunchKernelGGL(vecs_to_soa, dim3(nb), dim3(256), 0, nullptr, static_cast<const double2*>(r_dev),
+                           lat->defl_r, lat->g.V, m);
+        hipLaunchKernelGGL(vecs_to_soa, dim3(nb), dim3(256), 0, nullptr,
+                           static_cast<const double2*>(l_dev ? l_dev : r_dev), lat->defl_l, lat->g.V, m);
+        HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipMemcpy(lat->defl_sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+        HIP_TRY(ctx, hipDeviceSynchronize());
+    }
+    lat->defl_m = m;
+    return NKS_OK;
 }
 
 int nks_apply_op(nks_lattice* lat, const void* in, void* out, int dagger, int precision, void* stream) {

@@ -145,7 +145,16 @@ struct JobDesc {
     double* label;      // label mode output (LABEL_WORDS doubles), or null
     int* group;         // GROUP_WORDS ints shared by the jobs of one lattice group (zeroed by pack)
     int overlap;        // 1: the lift writes x = b + gamma5 y (overlap operator) instead of y
+    // deflation (App. C steps 1 and 6): dm eigenpairs of A held by the lattice
+    int dm;                 // 0 = no deflation
+    const double2* dr;      // right eigenvectors, SoA [i][comp][site] (complex128)
+    const double2* dl;      // left eigenvectors (= dr when A is Hermitian)
+    const double* dsgn;     // sgn(Re lambda_i)
+    double2* dcoef;         // <l_i, b> (written by pack_kernel, block 0)
+    double2* dpart;         // per-block partial sums of <l_i, b>, [i][block]
 };
+
+constexpr int DEFL_MAX = 64;   // deflated eigenpairs per lattice
 
 // Words shared by a lattice group: the largest learned k target of its jobs.
 enum GroupWord { GW_KTARGET_MAX = 0, GROUP_WORDS = 16 };
@@ -233,6 +242,7 @@ struct OuterLaunch {
     int precision;        // NKS_FP64 / NKS_MIXED
     int two_sided;
     Tuning tune;
+    int deflate;           // some job of the group is deflated
 };
 constexpr int OUTER_NT = 128;
 void launch_pack(const OuterLaunch& L, hipStream_t s);

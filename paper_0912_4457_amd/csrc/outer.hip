@@ -63,6 +63,26 @@ __device__ inline bool block_coords(int nblocks, int njobs, int xcd_map, int& sb
     return true;
 }
 
+// ------------------------------------------------------------------ deflation dots
+// Per-block partial sums of <l_i, b> = sum conj(l_i) b for every deflated job.
+__global__ __launch_bounds__(NT) void deflate_dots_kernel(JobDesc* jobs, int V, int nblocks) {
+    const JobDesc& J = jobs[blockIdx.y];
+    if (J.dm == 0) return;
+    __shared__ double2 lds[NT / 64];
+    const int site = blockIdx.x * NT + threadIdx.x;
+    const int n = 12 * V;
+    for (int i = 0; i < J.dm; ++i) {
+        double2 acc = mk(0.0, 0.0);
+        if (site < V) {
+            const double2* l = J.dl + (size_t)i * n;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc = cadd(acc, cmul(cconj(l[(size_t)c * V + site]), J.b[(size_t)12 * site + c]));
+        }
+        const double2 s = block_sum<NT>(acc, lds);
+        if (threadIdx.x == 0) J.dpart[(size_t)i * nblocks + blockIdx.x] = s;
+    }
+}
+
 // ------------------------------------------------------------------ pack
 template <typename R>
 __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblocks) {
@@ -76,13 +96,28 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
         J.status[threadIdx.x] = v;
     }
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < GROUP_WORDS && J.group) J.group[threadIdx.x] = 0;
+    // deflation (App. C step 1): b_m = b - sum_i <l_i, b> r_i, with the
+    // <l_i, b> re-reduced from deflate_dots' per-block partials by every block
+    __shared__ double2 dco[DEFL_MAX];
+    if (J.dm > 0) {
+        for (int i = 0; i < J.dm; ++i) {
+            const double2 d = sum_partials<NT>(J.dpart + (size_t)i * nblocks, nblocks, lds);
+            if (threadIdx.x == 0) {
+                dco[i] = d;
+                if (blockIdx.x == 0) J.dcoef[i] = d;
+            }
+        }
+        __syncthreads();
+    }
     double nb2 = 0.0;
     if (site < V) {
         cx_t<R>* u1 = column<R>(J, 1, n);
         cx_t<R>* t1 = J.two_sided ? lvec<R>(J, 1, n) : nullptr;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            cx_t<R> v = from_d2<R>(J.b[(size_t)12 * site + c]);
+            double2 bc = J.b[(size_t)12 * site + c];
+            for (int i = 0; i < J.dm; ++i) bc = csub(bc, cmul(dco[i], J.dr[(size_t)i * n + (size_t)c * V + site]));
+            cx_t<R> v = from_d2<R>(bc);
             u1[(size_t)c * V + site] = v;
             if (t1) t1[(size_t)c * V + site] = v;
             double2 d = to_d2<R>(v);
@@ -377,6 +412,8 @@ __global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
     }
     if (jj < kused) acc0 = cadd(acc0, cmul(J.omega[jj], to_d2<R>(base[(size_t)jj * n])));
     double2 y = cadd(acc0, acc1);
+    // deflation (App. C step 6): + sum_i sgn(lambda_i) <l_i, b> r_i
+    for (int i = 0; i < J.dm; ++i) y = cadd(y, cscale(cmul(J.dcoef[i], J.dr[(size_t)i * n + e]), J.dsgn[i]));
     if (J.overlap) {
         // D_ov(mu) b = b + gamma5 sgn(gamma5 D_w(mu)) b (Sec. 2, Eq. Dovmu); gamma5 = diag(1, 1, -1, -1)
         const double2 bv = J.b[(size_t)12 * s + c];
@@ -389,6 +426,7 @@ __global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
 
 void launch_pack(const OuterLaunch& L, hipStream_t s) {
     dim3 grid(L.nblocks, L.njobs);
+    if (L.deflate) hipLaunchKernelGGL(deflate_dots_kernel, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
     if (L.precision == NKS_FP64)
         hipLaunchKernelGGL(pack_kernel<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
     else
