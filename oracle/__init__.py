@@ -20,6 +20,8 @@ in float64/complex128, no blocking or fusion.  Modules:
 * ``nested``    -- the nested method of App. C (steps 2-6, no deflation),
                    the non-nested method (Eqs. non-nested, non-nested-oblique)
                    and the sgn^2 error estimate (Sec. 3).
+* ``multilevel`` -- multi-level nesting k_0 -> k_1 -> ... -> k_L with p per
+                   level (Sec. 4.5, Fig. 12).
 * ``policy``    -- ell-doubling and k-checkpoint rules (not in the paper).
 * ``mlp``       -- numpy MLP with bfloat16 weight rounding, forward, backward
                    and Adam (not in the paper).
