@@ -51,7 +51,10 @@
 extern "C" {
 #endif
 
-#define NKS_ABI_VERSION 1
+#define NKS_ABI_VERSION 2
+
+/* Largest number of nested levels (Sec. 4.5); see nks_opts.levels. */
+#define NKS_MAX_LEVELS 6
 
 enum nks_status {
     NKS_OK = 0,
@@ -94,6 +97,20 @@ typedef struct nks_opts {
     int max_rhi_iter;     /* Roberts-Higham iteration cap (default 50) */
     double rhi_tol;       /* relative Frobenius change that ends RHi (default 1e-14) */
     unsigned flags;       /* NKS_FLAG_* bits; others give NKS_E_INVALID */
+    /* Multi-level nesting (Sec. 4.5, Fig. 12).  levels = L nested levels,
+     * 1..NKS_MAX_LEVELS (1 = the nested method; default).  Level 0 is H_k; level
+     * i builds the Krylov space of size k_{i+1} of the preconditioned Ritz
+     * matrix of level i (Eq. precond with p_i), and RHi runs on the Ritz matrix
+     * of the deepest level.  k_1 = ell; ell_deep[i] = k_{i+2} for
+     * i < levels - 1 (each >= 1, rounded up to even).  A size that is not
+     * below the size of the level above makes that level exact (RHi on its
+     * Ritz matrix) and ends the recursion there.  p_deep[i] = p_{i+1} (<= 0:
+     * p_opt of Eq. popt from the Ritz values of that level; level 0 uses p).
+     * levels > 1 needs the FIXED ell policy and a FIXED or DOUBLING k policy
+     * (NKS_E_UNSUPPORTED otherwise). */
+    int levels;
+    int ell_deep[NKS_MAX_LEVELS - 1];
+    double p_deep[NKS_MAX_LEVELS - 1];
 } nks_opts;
 
 /* flags: return the overlap operator D_ov(mu) b = b + gamma5 sgn(A) b
@@ -120,6 +137,10 @@ typedef struct nks_stats {
     double inner_delta;   /* last ell-doubling relative change (policies), else 0 */
     double outer_delta;   /* last k-checkpoint relative change (policies), else 0 */
     float ms_outer, ms_nested, ms_lift;  /* device time per phase (single-job calls) */
+    int levels_used;      /* nested levels that ran (0 = non-nested; < opts.levels when a
+                             level was exact or the result came from a smaller setting) */
+    int ell_deep_used[NKS_MAX_LEVELS - 1];   /* k_{i+2} built at the deeper levels */
+    double p_deep_used[NKS_MAX_LEVELS - 1];  /* p_{i+1} used at the deeper levels */
 } nks_stats;
 
 typedef struct nks_ctx nks_ctx;
@@ -133,7 +154,8 @@ typedef struct nks_job {
     const nks_opts* opts;
 } nks_job;
 
-/* Fill *o with defaults: k=200, ell=50, tol=1e-8, FP64, p auto, FIXED policies. */
+/* Fill *o with defaults: k=200, ell=50, tol=1e-8, FP64, p auto, FIXED policies,
+ * one nested level. */
 void nks_opts_default(nks_opts* o);
 
 /* Create a context on HIP device `device` (makes it current). */
@@ -205,7 +227,8 @@ int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opt
 
 /* Steps 3-5 on a given tridiagonal H_k (host arrays as returned by
  * nks_outer_basis; hermitian != 0 treats it as real symmetric): returns
- * c ~ sgn(H_k) e_1 (k interleaved complex128 on the host).  Waits. */
+ * c ~ sgn(H_k) e_1 (k interleaved complex128 on the host), with
+ * opts.levels nested levels (Sec. 4.5).  Waits. */
 int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double* beta_host,
                     const double* gamma_host, int hermitian, const nks_opts* opts,
                     double* c_host, nks_stats* stats);

@@ -42,12 +42,16 @@ class NKSError(RuntimeError):
         self.code = code
 
 
+MAX_LEVELS = 6   # NKS_MAX_LEVELS
+
+
 class Opts(ctypes.Structure):
     _fields_ = [
         ("size", ctypes.c_size_t), ("k", ctypes.c_int), ("ell", ctypes.c_int), ("tol", ctypes.c_double),
         ("precision", ctypes.c_int), ("p", ctypes.c_double), ("k_policy", ctypes.c_int),
         ("ell_policy", ctypes.c_int), ("max_rhi_iter", ctypes.c_int), ("rhi_tol", ctypes.c_double),
-        ("flags", ctypes.c_uint),
+        ("flags", ctypes.c_uint), ("levels", ctypes.c_int),
+        ("ell_deep", ctypes.c_int * (MAX_LEVELS - 1)), ("p_deep", ctypes.c_double * (MAX_LEVELS - 1)),
     ]
 
 
@@ -58,10 +62,14 @@ class Stats(ctypes.Structure):
         ("z_max", ctypes.c_double), ("b_norm", ctypes.c_double), ("breakdown_iter", ctypes.c_int),
         ("inner_delta", ctypes.c_double), ("outer_delta", ctypes.c_double),
         ("ms_outer", ctypes.c_float), ("ms_nested", ctypes.c_float), ("ms_lift", ctypes.c_float),
+        ("levels_used", ctypes.c_int), ("ell_deep_used", ctypes.c_int * (MAX_LEVELS - 1)),
+        ("p_deep_used", ctypes.c_double * (MAX_LEVELS - 1)),
     ]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["ell_deep_used"] = list(self.ell_deep_used)[:max(self.levels_used - 1, 0)]
+        d["p_deep_used"] = list(self.p_deep_used)[:max(self.levels_used - 1, 0)]
         d["status_str"] = STATUS.get(self.status, "?")
         return d
 
@@ -139,7 +147,11 @@ FLAG_DEFLATE = 2
 
 
 def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50, rhi_tol=1e-14,
-              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False, deflate=False) -> Opts:
+              k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False, deflate=False,
+              ell_deep=(), p_deep=None) -> Opts:
+    """Options of one sign application.  ``ell_deep`` = sizes k_2, k_3, ...
+    of the deeper nested levels (Sec. 4.5; k_1 = ell), ``p_deep`` their p
+    (None or <= 0: estimated)."""
     o = Opts()
     lib().nks_opts_default(ctypes.byref(o))
     o.k, o.ell, o.tol = int(k), int(ell), float(tol)
@@ -148,6 +160,16 @@ def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50
     o.max_rhi_iter, o.rhi_tol = int(max_rhi_iter), float(rhi_tol)
     o.k_policy, o.ell_policy = int(k_policy), int(ell_policy)
     o.flags = (FLAG_OVERLAP if overlap else 0) | (FLAG_DEFLATE if deflate else 0)
+    ell_deep = list(ell_deep or ())
+    if len(ell_deep) > MAX_LEVELS - 1:
+        raise ValueError(f"at most {MAX_LEVELS - 1} deeper levels")
+    p_deep = list(p_deep) if p_deep is not None else [None] * len(ell_deep)
+    if len(p_deep) != len(ell_deep):
+        raise ValueError("p_deep needs one entry per deeper level")
+    o.levels = 1 + len(ell_deep)
+    for i, (e, q) in enumerate(zip(ell_deep, p_deep)):
+        o.ell_deep[i] = int(e)
+        o.p_deep[i] = 0.0 if q is None else float(q)
     return o
 
 
@@ -348,7 +370,8 @@ def sign_apply_batch(jobs, stats: bool = True):
         o = make_opts(k=j.get("k", 200), ell=j.get("ell", 50), tol=j.get("tol", 1e-8),
                       precision=j.get("precision", "fp64"), p=j.get("p"),
                       k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED),
-                      overlap=j.get("overlap", False), deflate=j.get("deflate", False))
+                      overlap=j.get("overlap", False), deflate=j.get("deflate", False),
+                      ell_deep=j.get("ell_deep", ()), p_deep=j.get("p_deep"))
         spec.append((lat, b, x, o))
         xs.append(x)
     ctx = spec[0][0].ctx
@@ -470,7 +493,7 @@ def mlp_adam_step(ctx: Context, params, grad, m, v, step: int, lr: float):
 
 def nested_step(ctx: Context, alpha, beta, gamma, hermitian: bool, ell: int, p: float | None = None,
                 max_rhi_iter: int = 50, rhi_tol: float = 1e-14, ell_policy: int = POLICY_FIXED,
-                tol: float = 1e-8):
+                tol: float = 1e-8, ell_deep=(), p_deep=None):
     """Steps 3-5 on a given tridiagonal H_k: returns (c ~ sgn(H_k) e_1, stats).
 
     With ell_policy=POLICY_DOUBLING, ``ell`` is the largest inner size allowed."""
@@ -478,7 +501,8 @@ def nested_step(ctx: Context, alpha, beta, gamma, hermitian: bool, ell: int, p: 
     k = alpha.size
     beta = np.ascontiguousarray(beta if k > 1 else np.zeros(1), dtype=np.complex128)
     gamma = np.ascontiguousarray(gamma if k > 1 else np.zeros(1), dtype=np.complex128)
-    o = make_opts(k=k, ell=ell, p=p, max_rhi_iter=max_rhi_iter, rhi_tol=rhi_tol, ell_policy=ell_policy, tol=tol)
+    o = make_opts(k=k, ell=ell, p=p, max_rhi_iter=max_rhi_iter, rhi_tol=rhi_tol, ell_policy=ell_policy, tol=tol,
+                  ell_deep=ell_deep, p_deep=p_deep)
     c = np.zeros(k, dtype=np.complex128)
     st = Stats()
     P = lambda arr_: arr_.view(np.float64).ctypes.data_as(_PD)  # noqa: E731

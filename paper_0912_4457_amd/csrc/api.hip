@@ -1,6 +1,7 @@
 // C ABI of libnks: contexts, lattices, workspace planning and the launch
 // sequence of a (batched) sign application.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
@@ -117,6 +118,9 @@ struct JobPlan {
     int group;          // index of its (lattice, precision) group
     int overlap;        // NKS_FLAG_OVERLAP
     int dm;             // deflated eigenpairs (NKS_FLAG_DEFLATE)
+    int levels;         // nested levels (multi-level nesting)
+    int ell_deep[NKS_MAX_LEVELS - 1];
+    double p_deep[NKS_MAX_LEVELS - 1];
     size_t off_dcoef, off_dpart;
     size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
         end;
@@ -130,6 +134,25 @@ struct Plan {
     size_t group_off = 0;     // GROUP_WORDS ints per group, after the job table
     size_t total = 0;
 };
+
+// Levels of a validated nks_opts: sizes rounded up to even, unused entries 0.
+void set_levels(int& levels, int* ell_deep, double* p_deep, const nks_opts* o) {
+    levels = o->levels;
+    for (int i = 0; i + 1 < NKS_MAX_LEVELS; ++i) {
+        const bool used = i + 1 < levels;
+        ell_deep[i] = used ? even_up(o->ell_deep[i]) : 0;
+        p_deep[i] = used ? o->p_deep[i] : 0.0;
+    }
+}
+
+void fill_level_stats(nks_stats& o, const int* st, const double* rp) {
+    o.levels_used = st[ST_LEVELS];
+    for (int i = 0; i + 1 < NKS_MAX_LEVELS; ++i) {
+        const bool ran = i + 1 < o.levels_used;
+        o.ell_deep_used[i] = ran ? st[ST_ELL_DEEP + i] : 0;
+        o.p_deep_used[i] = ran ? rp[RP_P_DEEP + i] : 0.0;
+    }
+}
 
 int validate_opts(nks_ctx* ctx, const nks_opts* o) {
     if (!o) return fail(ctx, NKS_E_INVALID, "opts is NULL");
@@ -148,6 +171,13 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
     if (o->flags & ~(unsigned)(NKS_FLAG_OVERLAP | NKS_FLAG_DEFLATE)) return fail(ctx, NKS_E_INVALID, "unknown flag bits");
     if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
         return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
+    if (o->levels < 1 || o->levels > NKS_MAX_LEVELS) return fail(ctx, NKS_E_INVALID, "levels must be in 1..NKS_MAX_LEVELS");
+    for (int i = 0; i + 1 < o->levels; ++i) {
+        if (o->ell_deep[i] < 1) return fail(ctx, NKS_E_INVALID, "ell_deep[i] must be >= 1 for i < levels - 1");
+        if (!std::isfinite(o->p_deep[i])) return fail(ctx, NKS_E_INVALID, "p_deep[i] must be finite");
+    }
+    if (o->levels > 1 && (o->ell_policy != NKS_POLICY_FIXED || o->k_policy == NKS_POLICY_LEARNED))
+        return fail(ctx, NKS_E_UNSUPPORTED, "levels > 1 needs the FIXED ell policy and a FIXED or DOUBLING k policy");
     return NKS_OK;
 }
 
@@ -174,6 +204,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.tol = J.opts->tol;
         jp.label = label;
         jp.overlap = (J.opts->flags & NKS_FLAG_OVERLAP) ? 1 : 0;
+        set_levels(jp.levels, jp.ell_deep, jp.p_deep, J.opts);
         jp.dm = 0;
         if (J.opts->flags & NKS_FLAG_DEFLATE) {
             if (J.lat->defl_m == 0)
@@ -222,7 +253,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.off_dcoef = off; off = align_up(off + sizeof(double2) * jp.dm);
         jp.off_dpart = off; off = align_up(off + sizeof(double2) * (size_t)jp.dm * jp.nblocks);
         jp.off_nest = off;
-        off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.two_sided) * (jp.label ? 1 + LABEL_NK : 1));
+        off = align_up(off + sizeof(double2) * nest_words(jp.k, jp.ell, jp.levels, jp.ell_deep) * (jp.label ? 1 + LABEL_NK : 1));
         jp.end = off;
     }
     P.total = off;
@@ -247,7 +278,7 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.max_rhi = jp.max_rhi;
     d.rhi_tol = jp.rhi_tol;
     d.two_sided = jp.two_sided;
-    d.nest_cap = (int)nest_words(jp.k, jp.ell, jp.two_sided);
+    d.nest_cap = (int)nest_words(jp.k, jp.ell, jp.levels, jp.ell_deep);
     d.lcap = jp.lcap;
     d.scstride = jp.k + 2;
     d.nblocks = jp.nblocks;
@@ -262,6 +293,11 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.net = jp.learned() ? ctx->net : nullptr;
     d.group = reinterpret_cast<int*>(ws + P.group_off) + (size_t)GROUP_WORDS * jp.group;
     d.overlap = jp.overlap;
+    d.levels = jp.levels;
+    for (int i = 0; i + 1 < NKS_MAX_LEVELS; ++i) {
+        d.ell_deep[i] = jp.ell_deep[i];
+        d.p_deep[i] = jp.p_deep[i];
+    }
     d.dm = jp.dm;
     if (jp.dm > 0) {
         d.dr = jp.lat->defl_r;
@@ -572,6 +608,7 @@ int read_stats(nks_ctx* ctx, const Plan& P, char* ws, bool timed, nks_stats* out
         o.ms_outer = t01;
         o.ms_nested = t12;
         o.ms_lift = t23;
+        fill_level_stats(o, st, rp);
     }
     return NKS_OK;
 }
@@ -594,6 +631,7 @@ void nks_opts_default(nks_opts* o) {
     o->max_rhi_iter = 50;
     o->rhi_tol = 1e-14;
     o->flags = 0;
+    o->levels = 1;
 }
 
 int nks_create(int device, nks_ctx** out) {
@@ -862,7 +900,11 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
     const size_t off_st = off; off = align_up(off + sizeof(int) * ST_COUNT);
     const size_t off_rp = off; off = align_up(off + sizeof(double) * RP_COUNT);
     const size_t off_om = off; off = align_up(off + sizeof(double2) * k);
-    const size_t off_ne = off; off = align_up(off + sizeof(double2) * nest_words(k, ell, !hermitian));
+    int levels, ell_deep[NKS_MAX_LEVELS - 1];
+    double p_deep[NKS_MAX_LEVELS - 1];
+    set_levels(levels, ell_deep, p_deep, opts);
+    const size_t nwords = nest_words(k, ell, levels, ell_deep);
+    const size_t off_ne = off; off = align_up(off + sizeof(double2) * nwords);
     char* w = nullptr;
     HIP_TRY(ctx, hipMalloc(&w, off));
     std::unique_ptr<char, decltype(&hipFree)> guard(w, &hipFree);
@@ -894,8 +936,13 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
     d.max_rhi = opts->max_rhi_iter;
     d.rhi_tol = opts->rhi_tol;
     d.two_sided = !hermitian;
-    d.nest_cap = (int)nest_words(k, ell, !hermitian);
+    d.nest_cap = (int)nwords;
     d.lcap = lcap;
+    d.levels = levels;
+    for (int i = 0; i + 1 < NKS_MAX_LEVELS; ++i) {
+        d.ell_deep[i] = ell_deep[i];
+        d.p_deep[i] = p_deep[i];
+    }
     d.scstride = (int)stride;
     d.precision = NKS_FP64;
     d.k_policy = NKS_POLICY_FIXED;
@@ -922,6 +969,7 @@ int nks_nested_step(nks_ctx* ctx, int k, const double* alpha_host, const double*
         stats->z_max = rp[RP_ZMAX];
         stats->b_norm = 1.0;
         stats->inner_delta = rp[RP_INNER_DELTA];
+        fill_level_stats(*stats, st, rp);
     }
     return NKS_OK;
 }

@@ -370,14 +370,14 @@ __device__ void apply_hprime(const NestPtrs& P, int k, double p, const T* v, T* 
 }
 
 // Sturm count: number of eigenvalues < x of the real symmetric tridiagonal (d, e^2)
-__device__ inline int sturm_count(const double2* d, const double2* sub, int k, double x, double pivmin) {
+__device__ inline int sturm_count(const double* d, const double* sub, int k, double x, double pivmin) {
     int cnt = 0;
-    double q = d[0].x - x;
+    double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
     for (int i = 1; i < k; ++i) {
-        const double e = sub[i - 1].x;
-        q = d[i].x - x - e * e / q;
+        const double e = sub[i - 1];
+        q = d[i] - x - e * e / q;
         if (fabs(q) < pivmin) q = -pivmin;
         if (q < 0.0) ++cnt;
     }
@@ -385,7 +385,7 @@ __device__ inline int sturm_count(const double2* d, const double2* sub, int k, d
 }
 
 // m-th smallest eigenvalue (1-based) by 256-way multisection of [-G, G]
-__device__ double find_eig(const double2* d, const double2* sub, int k, int m, double G, double pivmin,
+__device__ double find_eig(const double* d, const double* sub, int k, int m, double G, double pivmin,
                            double* ldsd) {
     double lo = -G, hi = G;
     for (int round = 0; round < 4; ++round) {
@@ -639,24 +639,24 @@ struct Smem {
 };
 
 // ---------------------------------------------------------------- step 3: p
-// Estimated Ritz-value extremes of the tridiagonal H_k (in P.d/sub/sup).
+// Estimated Ritz-value extremes of the tridiagonal in P.d/sub/sup (H_k, or
+// the Ritz matrix of a deeper level).
 template <typename T>
-__device__ void estimate_extremes(const JobDesc& J, const NestPtrs& P, int k, const Smem& sm, double& zmin,
-                                  double& zmax) {
+__device__ void estimate_extremes(const NestPtrs& P, int k, const Smem& sm, double& zmin, double& zmax) {
     constexpr bool CPLX = sizeof(T) == sizeof(double2);
     const int tid = threadIdx.x;
     const T* d = (const T*)P.d;
     const T* sub = (const T*)P.sub;
     const T* sup = (const T*)P.sup;
     if (!CPLX) {
-        // Ritz values of the real symmetric H_k by Sturm multisection
-        const double2* dd = (const double2*)(J.sc + (size_t)SC_ALPHA * J.scstride + 1);
-        const double2* ee = (const double2*)(J.sc + (size_t)SC_BETA * J.scstride + 1);
+        // Ritz values of the real symmetric matrix by Sturm multisection
+        const double* dd = (const double*)P.d;
+        const double* ee = (const double*)P.sub;
         double g = 0.0, emax = 0.0;
         for (int i = tid; i < k; i += NT) {
-            const double el = (i > 0) ? fabs(ee[i - 1].x) : 0.0;
-            const double er = (i + 1 < k) ? fabs(ee[i].x) : 0.0;
-            g = fmax(g, fabs(dd[i].x) + el + er);
+            const double el = (i > 0) ? fabs(ee[i - 1]) : 0.0;
+            const double er = (i + 1 < k) ? fabs(ee[i]) : 0.0;
+            g = fmax(g, fabs(dd[i]) + el + er);
             emax = fmax(emax, er);
         }
         const double G = block_max(g, sm.redd) * 1.001 + 1e-300;
@@ -983,10 +983,123 @@ __device__ double rel_change(const T* a, const T* b, int k, const Smem& sm) {   
 
 struct NestResult {
     int ell = 0;        // inner size of the accepted result (0 = non-nested)
+    int levels = 0;     // nested levels that ran (0 = non-nested)
     int rhi = 0;        // RHi iterations (negative: no convergence)
     int status = NKS_OK;
     double p = 0.0, zmin = 0.0, zmax = 0.0, inner_delta = 0.0;
 };
+
+// ---------------------------------------------------------------- multi-level nesting (Sec. 4.5)
+// Words of the deeper levels' nest areas, after level 0's.  Level i >= 1
+// holds a tridiagonal of at most cap_i (cap_1 = the level-1 capacity) and
+// builds min(ell_deep[i - 1], cap_i) inner vectors; a size that is not below
+// cap_i ends the chain, as it makes level i exact.
+__host__ __device__ inline size_t deep_words_impl(int cap1, int levels, const int* ell_deep) {
+    size_t w = 0;
+    int cap = cap1;
+    for (int i = 1; i < levels; ++i) {
+        const int want = ell_deep[i - 1] < cap ? ell_deep[i - 1] : cap;
+        if (want >= cap) break;
+        w += nest_words_impl(cap, want);
+        cap = want;
+    }
+    return w;
+}
+
+// Nest area of deeper level i (1 <= i < levels, within the chain above).
+__device__ inline NestPtrs deep_ptrs(const JobDesc& J, int i) {
+    double2* base = J.nest + nest_words_impl(J.k, J.lcap);
+    int cap = J.lcap;
+    for (int l = 1; l < i; ++l) {
+        const int want = min(J.ell_deep[l - 1], cap);
+        base += nest_words_impl(cap, want);
+        cap = want;
+    }
+    return nest_ptrs(base, cap, min(J.ell_deep[i - 1], cap));
+}
+
+// out (k) = W s with the inner basis W of a level (m columns of length k)
+template <typename T>
+__device__ void basis_times(const NestPtrs& P, int k, int m, const T* s, T* out) {
+    const T* vl = (const T*)P.vl;
+    for (int q = threadIdx.x; q < k; q += NT) {
+        T acc = s_zero<T>();
+        for (int j = 0; j < m; ++j) acc = s_add(acc, s_mul(vl[(size_t)j * k + q], s[j]));
+        out[q] = acc;
+    }
+    __syncthreads();
+}
+
+// Level 0 has built its inner space: T_1 (size m) in P0.al/bl/gl and W_0 in
+// P0.vl.  Each deeper level i runs steps 3 and 4 on T_i (p_i given, or p_opt
+// from T_i's Ritz extremes): the LU of p_i T_i and the (two-sided) Lanczos
+// process on T_i' from e_1, giving T_{i+1} and W_i.  RHi runs on the deepest
+// T_L and the result is lifted through every basis,
+// c = W_0 W_1 ... W_{L-1} sgn(T_L) e_1 -> out (k0).  Returns the RHi
+// iterations; levels, sizes and p go to res and the job's report words.
+template <typename T>
+__device__ int deep_coeffs(const JobDesc& J, const NestPtrs& P0, int k0, int m, T* out, const Smem& sm,
+                           NestResult& res) {
+    const int tid = threadIdx.x;
+    __shared__ int nsz[NKS_MAX_LEVELS + 1];
+    if (tid == 0) {
+        nsz[0] = k0;
+        nsz[1] = m;
+        for (int i = 0; i + 1 < NKS_MAX_LEVELS; ++i) {
+            J.status[ST_ELL_DEEP + i] = 0;
+            J.report[RP_P_DEEP + i] = 0.0;
+        }
+    }
+    __syncthreads();
+    int depth = 1;   // levels whose inner space exists
+    int cap = J.lcap;
+    for (int i = 1; i < J.levels; ++i) {
+        const int ni = nsz[i];
+        const int want = min(J.ell_deep[i - 1], ni);
+        const int want_cap = min(J.ell_deep[i - 1], cap);
+        if (want >= ni || want_cap >= cap) break;   // level i is exact
+        cap = want_cap;
+        const NestPtrs Q = deep_ptrs(J, i);
+        const NestPtrs U = (i == 1) ? P0 : deep_ptrs(J, i - 1);
+        T* d = (T*)Q.d;
+        T* sub = (T*)Q.sub;
+        T* sup = (T*)Q.sup;
+        for (int q = tid; q < ni; q += NT) {
+            d[q] = ((const T*)U.al)[q];
+            if (q + 1 < ni) { sub[q] = ((const T*)U.bl)[q]; sup[q] = ((const T*)U.gl)[q]; }
+        }
+        __syncthreads();
+        double p = J.p_deep[i - 1];
+        if (p <= 0.0) {
+            double zmin, zmax;
+            estimate_extremes<T>(Q, ni, sm, zmin, zmax);
+            p = 1.0 / sqrt(zmin * zmax);
+            if (!(p > 0.0) || !isfinite(p)) p = 1.0;
+        }
+        if (lu_pH<T>(Q, ni, p) != 0) { res.status = NKS_E_NOCONV; break; }
+        Inner in;
+        inner_init<T>(Q, ni, p, in, sm);
+        inner_extend<T>(Q, ni, p, want, in, sm);
+        if (in.serious) res.status = NKS_E_BREAKDOWN;
+        if (tid == 0) {
+            nsz[i + 1] = in.i;
+            J.status[ST_ELL_DEEP + i - 1] = in.i;
+            J.report[RP_P_DEEP + i - 1] = p;
+        }
+        __syncthreads();
+        depth = i + 1;
+    }
+    res.levels = depth;
+    // RHi on T_depth, lifted through W_{depth-1}, then through the bases above
+    const NestPtrs B = (depth == 1) ? P0 : deep_ptrs(J, depth - 1);
+    const int it = inner_coeffs<T>(J, B, nsz[depth - 1], nsz[depth], depth == 1 ? out : (T*)B.cc, sm);
+    for (int i = depth - 2; i >= 0; --i) {
+        const NestPtrs Pi = (i == 0) ? P0 : deep_ptrs(J, i);
+        const NestPtrs Pn = deep_ptrs(J, i + 1);
+        basis_times<T>(Pi, nsz[i], nsz[i + 1], (const T*)Pn.cc, i == 0 ? out : (T*)Pi.cc);
+    }
+    return it;
+}
 
 // H_k (k = kk) from the job's scalars into the nest area
 template <typename T>
@@ -1027,7 +1140,7 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     }
     double p = J.p;
     if (p <= 0.0) {
-        estimate_extremes<T>(J, P, kk, sm, res.zmin, res.zmax);
+        estimate_extremes<T>(P, kk, sm, res.zmin, res.zmax);
         p = 1.0 / sqrt(res.zmin * res.zmax);
         if (!(p > 0.0) || !isfinite(p)) p = 1.0;   // degenerate estimate: p = 1 is one RHi step
     }
@@ -1035,9 +1148,11 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     if (lu_pH<T>(P, kk, p) != 0) { res.status = NKS_E_NOCONV; return res; }
     Inner in;
     inner_init<T>(P, kk, p, in, sm);
+    res.levels = 1;
     if (!doubling) {
         inner_extend<T>(P, kk, p, min(ell0, cap), in, sm);
-        res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
+        if (J.levels > 1) res.rhi = deep_coeffs<T>(J, P, kk, in.i, cc, sm, res);
+        else res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
         res.ell = in.i;
     } else {
         int ell = min(ell0, cap);
@@ -1051,6 +1166,7 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
                 res.rhi = nonnested_coeffs<T>(J, P, kk, cc, sm);
                 res.inner_delta = rel_change<T>(cc, cp, kk, sm);
                 res.ell = 0;
+                res.levels = 0;
                 if (trace && step < ntrace && tid == 0) trace[step] = res.inner_delta;
                 break;
             }
@@ -1094,10 +1210,10 @@ template <typename T>
 __device__ void job_features(const JobDesc& J, const NestPtrs& P, int k0, const Smem& sm, double* f) {
     double zmin, zmax, zmin2, zmax2;
     load_H<T>(J, P, k0);
-    estimate_extremes<T>(J, P, k0, sm, zmin, zmax);
+    estimate_extremes<T>(P, k0, sm, zmin, zmax);
     const int kh = max(2, k0 / 2);
     load_H<T>(J, P, kh);
-    estimate_extremes<T>(J, P, kh, sm, zmin2, zmax2);
+    estimate_extremes<T>(P, kh, sm, zmin2, zmax2);
     const double2* sc = J.sc;
     const size_t st = J.scstride;
     double sa = 0.0, sb = 0.0;
@@ -1185,6 +1301,7 @@ __device__ void write_result(const JobDesc& J, const T* cc, int kk, const NestRe
             status = NKS_E_NOCONV;
         J.status[ST_STATUS] = status;
         J.status[ST_ELL] = res.ell;
+        J.status[ST_LEVELS] = res.levels;
         J.status[ST_RHI] = res.rhi < 0 ? -res.rhi : res.rhi;
         J.report[RP_P] = res.p;
         J.report[RP_ZMIN] = res.zmin;
@@ -1398,9 +1515,9 @@ __global__ __launch_bounds__(NT) void finalize_kernel(JobDesc* jobs) {
 
 }  // namespace
 
-size_t nest_words(int k, int ell, int /*two_sided*/) {
+size_t nest_words(int k, int ell, int levels, const int* ell_deep) {
     const int L = ell >= k ? k : ell;
-    return nest_words_impl(k, L);
+    return nest_words_impl(k, L) + (ell < k ? deep_words_impl(L, levels, ell_deep) : 0);
 }
 
 void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s) {

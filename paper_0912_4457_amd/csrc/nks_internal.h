@@ -95,7 +95,9 @@ enum StatusWord {
     ST_KTARGET = 9,     // learned policy: predicted outer size (0 = none)
     ST_ELLSTART = 10,   // learned policy: first inner size of the doubling (0 = default)
     ST_FALLBACK = 11,   // learned policy: prediction rejected, plain checkpoints took over
-    ST_COUNT = 16
+    ST_LEVELS = 12,     // nested levels that ran (multi-level nesting)
+    ST_ELL_DEEP = 13,   // .. 13 + NKS_MAX_LEVELS - 2: sizes built at the deeper levels
+    ST_COUNT = 24
 };
 
 // doubles reported by the nested step
@@ -106,7 +108,8 @@ enum ReportWord {
     RP_ZMAX = 3,
     RP_INNER_DELTA = 4,
     RP_OUTER_DELTA = 5,
-    RP_COUNT = 8
+    RP_P_DEEP = 8,      // .. 8 + NKS_MAX_LEVELS - 2: p of the deeper levels
+    RP_COUNT = 16
 };
 
 // Partial-sum slots (each an array of double2 of length nblocks).
@@ -152,7 +155,14 @@ struct JobDesc {
     const double* dsgn;     // sgn(Re lambda_i)
     double2* dcoef;         // <l_i, b> (written by pack_kernel, block 0)
     double2* dpart;         // per-block partial sums of <l_i, b>, [i][block]
+    // multi-level nesting (Sec. 4.5): levels >= 1; level i + 1 < levels builds
+    // ell_deep[i] vectors (even) with p_deep[i] (<= 0: estimate)
+    int levels;
+    int ell_deep[NKS_MAX_LEVELS - 1];
+    double p_deep[NKS_MAX_LEVELS - 1];
 };
+static_assert(ST_ELL_DEEP + NKS_MAX_LEVELS - 1 <= ST_COUNT && RP_P_DEEP + NKS_MAX_LEVELS - 1 <= RP_COUNT,
+              "status / report words of the deeper levels");
 
 constexpr int DEFL_MAX = 64;   // deflated eigenpairs per lattice
 
@@ -257,7 +267,7 @@ void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // after R_j
 void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s);      // after R_{k0}
 void launch_label(JobDesc* jobs, int njobs, hipStream_t s);               // after the outer loop
-size_t nest_words(int k, int ell, int two_sided);
+size_t nest_words(int k, int ell, int levels, const int* ell_deep);
 
 // mlp.hip
 int mlp_nparams();

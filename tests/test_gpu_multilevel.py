@@ -1,0 +1,189 @@
+"""GPU parity of multi-level nesting (Sec. 4.5, Fig. 12): the nested step with
+deeper levels on the oracle's own H_k, the whole sign application against
+the oracle's multi-level method, the pure-gauge closed form at the full
+10^4 size, and the option checks of the C ABI."""
+import ctypes
+import functools
+
+import numpy as np
+import pytest
+
+import nks_inputs as I
+from gpu_common import ctx, lattice, operator, rel, to_np
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4, 4, 4, 4)
+SIZES = [60, 20, 8, 4, 2]
+
+
+@functools.lru_cache(maxsize=None)
+def ritz(mu, k):
+    from oracle import krylov
+    op = operator(DIMS, 0.5, 4401, mu)
+    b = I.gaussian_source(DIMS, 4402).ravel()
+    if mu == 0.0:
+        return krylov.lanczos(op.matvec, b, k)
+    return krylov.two_sided_lanczos(op.matvec, op.rmatvec, b, k)
+
+
+def _sensitivity_tol(kr, herm, sizes, ps, c_ref):
+    # two-sided: the inner recurrences amplify rounding; allow ten times the
+    # oracle's own response to two-ulp changes of alpha (three draws)
+    from oracle import multilevel
+    if herm:
+        return 1e-11
+    resp = 0.0
+    for seed_ in (1, 2, 3):
+        rng = np.random.default_rng(seed_)
+        a2 = kr.alpha * (1 + 4e-16 * rng.choice([-1.0, 1.0], kr.alpha.shape))
+        c2, _ = multilevel.multilevel_coefficients(a2, kr.beta, kr.gamma, herm, sizes, ps)
+        resp = max(resp, rel(c2, c_ref))
+    return max(1e-10, 10 * resp)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+@pytest.mark.parametrize("depth", [2, 3, 5])
+def test_nested_step_levels_match_oracle_at_given_p(mu, depth):
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel
+    kr = ritz(mu, 300)
+    herm = mu == 0.0
+    sizes = SIZES[:depth]
+    c_ref, info = multilevel.multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, herm, sizes)
+    assert info["levels"] == depth
+    c, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, sizes[0], p=info["p"][0],
+                            ell_deep=sizes[1:], p_deep=info["p"][1:])
+    assert st["status"] == 0 and st["levels_used"] == depth
+    assert [st["ell_used"]] + st["ell_deep_used"] == info["sizes"][1:]
+    assert np.allclose(st["p_deep_used"], info["p"][1:], rtol=0, atol=0)
+    assert rel(c, c_ref) <= _sensitivity_tol(kr, herm, sizes, info["p"], c_ref)
+
+
+def test_nested_step_levels_estimate_p_like_the_oracle():
+    # Hermitian levels: Sturm multisection finds the same Ritz extremes as the
+    # oracle's eigensolver, so every p and the result agree closely
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel
+    kr = ritz(0.0, 300)
+    c_ref, info = multilevel.multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, True, SIZES)
+    c, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, True, SIZES[0], ell_deep=SIZES[1:])
+    assert st["levels_used"] == 5
+    assert np.allclose([st["p_used"]] + st["p_deep_used"], info["p"], rtol=1e-9)
+    assert rel(c, c_ref) <= 1e-9
+
+
+def test_nested_step_two_sided_levels_converge():
+    # two-sided levels estimate p by inverse / power iteration: the p values
+    # differ from the oracle's exact ones, the converged result does not
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel, signfun
+    kr = ritz(0.3, 300)
+    c_ref, info = multilevel.multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, False, SIZES)
+    c, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, False, SIZES[0], ell_deep=SIZES[1:])
+    assert st["status"] == 0 and st["levels_used"] == 5
+    assert np.allclose([st["p_used"]] + st["p_deep_used"], info["p"], rtol=0.05)
+    s = signfun.sign_eig(kr.H(), hermitian=False)[:, 0]
+    assert rel(c, s) <= 3 * rel(c_ref, s) + 1e-12
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_exact_deeper_level_is_the_one_level_method(mu):
+    # a deeper size not below the level above makes that level exact
+    import paper_0912_4457_amd as nks
+    kr = ritz(mu, 300)
+    herm = mu == 0.0
+    c1, s1 = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, 60, p=1.7)
+    c2, s2 = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, 60, p=1.7, ell_deep=[60, 8])
+    assert s1["levels_used"] == 1 and s2["levels_used"] == 1 and s2["ell_deep_used"] == []
+    assert np.array_equal(c1, c2)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_sign_apply_levels_match_oracle(mu):
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel
+    lat = lattice(DIMS, 0.5, 4401, mu)
+    op = operator(DIMS, 0.5, 4401, mu)
+    b = I.gaussian_source(DIMS, 4402)
+    y_ref, info = multilevel.sign_apply(op, b, 200, SIZES)
+    x, st = nks.sign_apply(lat, b.ravel(), k=200, ell=SIZES[0], p=info["p"][0], ell_deep=SIZES[1:],
+                           p_deep=info["p"][1:])
+    assert st["status"] == 0 and st["levels_used"] == 5 and st["k_used"] == info["k"]
+    assert rel(to_np(x), y_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_levels_in_a_batch_equal_single_calls(precision):
+    import paper_0912_4457_amd as nks
+    la = lattice(DIMS, 0.5, 4401, 0.0)
+    lb = lattice(DIMS, 0.5, 4401, 0.3)
+    jobs = [dict(lat=la, b=I.gaussian_source(DIMS, 1).ravel(), k=120, ell=40, ell_deep=[12, 4]),
+            dict(lat=la, b=I.gaussian_source(DIMS, 2).ravel(), k=120, ell=40),
+            dict(lat=lb, b=I.gaussian_source(DIMS, 3).ravel(), k=120, ell=40, ell_deep=[16, 6, 2]),
+            dict(lat=lb, b=I.gaussian_source(DIMS, 4).ravel(), k=100, ell=30, ell_deep=[8])]
+    for j in jobs:
+        j["precision"] = precision
+    xs, sts = nks.sign_apply_batch(jobs)
+    for j, x, st in zip(jobs, xs, sts):
+        y, s1 = nks.sign_apply(j["lat"], j["b"], k=j["k"], ell=j["ell"], precision=precision,
+                               ell_deep=j.get("ell_deep", ()))
+        assert st["levels_used"] == 1 + len(j.get("ell_deep", ()))
+        assert np.array_equal(to_np(x), to_np(y))
+
+
+def test_levels_with_k_checkpoints():
+    # the k policy evaluates every checkpoint with the same levels
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel
+    lat = lattice(DIMS, 0.5, 4401, 0.0)
+    op = operator(DIMS, 0.5, 4401, 0.0)
+    b = I.gaussian_source(DIMS, 4402)
+    x, st = nks.sign_apply(lat, b.ravel(), k=800, ell=60, tol=1e-9, k_policy=nks.POLICY_DOUBLING,
+                           ell_deep=[20, 8])
+    assert st["status"] == 0 and st["levels_used"] == 3 and st["k_used"] < 800
+    y_ref, info = multilevel.sign_apply(op, b, st["k_used"], [60, 20, 8])
+    assert rel(to_np(x), y_ref) <= 1e-9
+
+
+# (the oracle's five-level error at these sizes: 4.3e-12 and 1.5e-13)
+@pytest.mark.parametrize("mu,k,ell", [(0.0, 160, 60), (0.2, 400, 100)])
+def test_levels_meet_pure_gauge_closed_form_10x4(mu, k, ell):
+    import paper_0912_4457_amd as nks
+    from oracle import closedform
+    dims = (10, 10, 10, 10)
+    g = I.random_su3_field(dims, 1234)
+    lat = lattice(dims, 0.0, 1234, mu, kind="pure")
+    b = I.gaussian_source(dims, 99)
+    ref = closedform.pure_gauge_sign_apply(b, g, dims, 1.6, mu)
+    x, st = nks.sign_apply(lat, b.ravel(), k=k, ell=ell, ell_deep=[ell // 3, 8, 4, 2])
+    assert st["status"] == 0 and st["levels_used"] == 5
+    assert rel(to_np(x), ref) <= 1e-10
+
+
+def _rc(**kw):
+    import paper_0912_4457_amd as nks
+    lat = lattice(DIMS, 0.5, 4401, 0.0)
+    import torch
+    b = torch.from_numpy(I.gaussian_source(DIMS, 3).ravel()).cuda()
+    x = torch.empty_like(b)
+    o = nks.make_opts(k=60, ell=20)
+    for key, v in kw.items():
+        if key in ("ell_deep", "p_deep"):
+            for i, e in enumerate(v):
+                getattr(o, key)[i] = e
+        else:
+            setattr(o, key, v)
+    ws = lat.ctx.workspace(1 << 26)
+    return nks.lib().nks_sign_apply(lat.ctx.h, lat.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, None)
+
+
+def test_level_options_are_checked():
+    import paper_0912_4457_amd as nks
+    assert _rc(levels=0) == 1
+    assert _rc(levels=nks.MAX_LEVELS + 1) == 1
+    assert _rc(levels=3, ell_deep=[8, 0]) == 1
+    assert _rc(levels=2, ell_deep=[8], p_deep=[float("inf")]) == 1
+    assert _rc(levels=2, ell_deep=[8], ell_policy=nks.POLICY_DOUBLING, tol=1e-8) == 4
+    assert _rc(levels=2, ell_deep=[8]) == 0

@@ -46,6 +46,34 @@ def test_status_strings_and_defaults_without_gpu():
     assert o.size == ctypes.sizeof(nks.Opts)
     assert (o.k, o.ell, o.precision, o.max_rhi_iter) == (200, 50, 0, 50)
     assert o.rhi_tol == pytest.approx(1e-14)
+    assert o.levels == 1 and list(o.ell_deep) == [0] * (nks.MAX_LEVELS - 1)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors have the C sizes and field offsets (gcc on the header)
+    import shutil
+    import subprocess
+    import paper_0912_4457_amd as nks
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    fields = {"nks_opts": nks.Opts, "nks_stats": nks.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
+    lines.append('printf("%d\\n", NKS_MAX_LEVELS); return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for cls in fields.values():
+        want.append(ctypes.sizeof(cls))
+        want.extend(getattr(cls, f).offset for f, _ in cls._fields_)
+    want.append(nks.MAX_LEVELS)
+    assert got == want
 
 
 def test_invalid_device_rejected_without_gpu():
