@@ -210,6 +210,110 @@ def overlap_path(nks, torch, ctx, gold, steps):
             "max_rel_err_vs_oracle": max(errs) if errs else None}
 
 
+def multilevel_path(nks, torch, ctx, gold, steps):
+    """Multi-level nesting (Sec. 4.5) on the same 24 jobs: ell = 64 -> 32 -> 16
+    -> 8 -> 4 (RHi on a 4 x 4 matrix) against the one-level nested step, with
+    the nested kernel's own device time (HIP events on every nested launch of
+    4 calls, the lattice groups one after another)."""
+    out = {}
+    for name, deep in (("one_level", ()), ("five_levels", (32, 16, 8, 4))):
+        lats, jobs = make_jobs(nks, torch, ctx, "fp64", ell_deep=deep)
+        dt = time_calls(nks, torch, jobs, steps, 1)
+        ctx.tune_set("concurrent_groups", 0)
+        ctx.profile(True)
+        for _ in range(4):
+            nks.sign_apply_batch(jobs, stats=False)
+        torch.cuda.synchronize()
+        n, ms, _ = ctx.profile_read("nested")
+        for kc in ("stencil", "recurrence", "lift"):      # release the other classes' events
+            ctx.profile_read(kc)
+        ctx.profile(False)
+        ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
+        xs, sts = nks.sign_apply_batch(jobs, stats=True)
+        torch.cuda.synchronize()
+        errs = errors_vs_golden(jobs, xs, gold)
+        out[name] = {"ell": [ELL] + list(deep), "value": len(jobs) * steps / dt,
+                     "nested_ms": ms / n if n else None,
+                     "max_rel_err_vs_oracle": max(errs) if errs else None,
+                     "levels_used": sorted(set(s["levels_used"] for s in sts)),
+                     "rhi_iters": sorted(set(s["rhi_iters"] for s in sts))}
+        log(f"[bench] {name}: {out[name]['value']:.1f} app/s, nested {out[name]['nested_ms']} ms, "
+            f"err {out[name]['max_rel_err_vs_oracle']}")
+        for lat in lats:
+            lat.close()
+    out["unit"] = "applications/s"
+    return out
+
+
+def workspace_bytes(nks, ctx, jobs):
+    import ctypes
+    opts = [nks.make_opts(k=j["k"], ell=j["ell"], double_pass=j.get("double_pass", False)) for j in jobs]
+    arr = (nks.Job * len(jobs))()
+    for i, (j, o) in enumerate(zip(jobs, opts)):
+        arr[i].lat, arr[i].b, arr[i].x = j["lat"].h.value, j["b"].data_ptr(), j["x"].data_ptr()
+        arr[i].opts = ctypes.pointer(o)
+    sz = ctypes.c_size_t()
+    ctx.check(nks.lib().nks_workspace_size(ctx.h, len(jobs), arr, ctypes.byref(sz)))
+    return sz.value
+
+
+def double_pass_path(nks, torch, ctx, gold, steps, large=True):
+    """Double-pass mode (Sec. 4.4): the same 24 jobs (results identical to the
+    single-pass ones bit for bit), and 24 point sources on a 24^4 lattice,
+    whose single-pass basis store at k = 500 would not fit in HBM."""
+    import numpy as np
+    lats, jobs = make_jobs(nks, torch, ctx, "fp64", double_pass=True)
+    dt = time_calls(nks, torch, jobs, steps, 1)
+    xs, sts = nks.sign_apply_batch(jobs, stats=True)
+    torch.cuda.synchronize()
+    errs = errors_vs_golden(jobs, xs, gold)
+    out = {"value": len(jobs) * steps / dt, "unit": "applications/s",
+           "max_rel_err_vs_oracle": max(errs) if errs else None,
+           "workspace_GB": workspace_bytes(nks, ctx, jobs) / 1e9,
+           "single_pass_workspace_GB": workspace_bytes(nks, ctx, [dict(j, double_pass=False) for j in jobs]) / 1e9}
+    for lat in lats:
+        lat.close()
+    log(f"[bench] double pass 10^4: {out['value']:.1f} app/s, err {out['max_rel_err_vs_oracle']}, "
+        f"workspace {out['workspace_GB']:.2f} GB (single pass {out['single_pass_workspace_GB']:.1f} GB)")
+    if not large:
+        return out
+    import nks_inputs as I
+    dims = (24, 24, 24, 24)
+    links = I.su3_links(dims, EPS, LINK_SEED)
+    big = []
+    blats = []
+    for mu in MUS:
+        lat = nks.Lattice(ctx, dims, links, m0=M0, mu=mu)
+        blats.append(lat)
+        for spin in range(4):
+            for colour in range(3):
+                b = torch.from_numpy(I.point_source(dims, spin, colour).ravel()).cuda()
+                big.append(dict(lat=lat, b=b, x=torch.empty_like(b), k=K, ell=ELL, double_pass=True, mu=mu))
+    nks.sign_apply_batch(big, stats=False)                 # warm (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, _ = nks.sign_apply_batch(big, stats=False)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    # accuracy by the sgn^2 estimate of Sec. 3 on one source per mu
+    est = []
+    for idx in (0, len(big) // 2):
+        j = big[idx]
+        x2, _ = nks.sign_apply(j["lat"], xs[idx], k=K, ell=ELL, double_pass=True, stats=False)
+        torch.cuda.synchronize()
+        est.append(float(torch.linalg.vector_norm(x2 - j["b"]) / (2 * torch.linalg.vector_norm(j["b"]))))
+    out["large"] = {"lattice": "24^4", "jobs": len(big), "k": K, "ell": ELL, "value": len(big) / dtb,
+                    "seconds_per_call": dtb, "workspace_GB": workspace_bytes(nks, ctx, big) / 1e9,
+                    "single_pass_workspace_GB": workspace_bytes(nks, ctx, [dict(j, double_pass=False)
+                                                                          for j in big]) / 1e9,
+                    "sgn2_error_estimate": est}
+    log(f"[bench] double pass 24^4: {out['large']['value']:.2f} app/s, sgn^2 estimate {est}, "
+        f"workspace {out['large']['workspace_GB']:.1f} GB (single pass {out['large']['single_pass_workspace_GB']:.0f} GB)")
+    for lat in blats:
+        lat.close()
+    return out
+
+
 def uneven_batch(nks, torch, ctx, steps):
     """64 point sources over nine lattices (6^4, 8^4, 10^4 x mu in {0, 0.1,
     0.3}) with tolerances 1e-6 / 1e-8, in one batched call: plain policies
@@ -368,12 +472,16 @@ def main():
     ctx.tune_set("concurrent_groups", 0 if SERIAL_GROUPS else 1)
     for lat in lats_g:
         lat.close()
-    paths = uneven = overlap_res = None
+    paths = uneven = overlap_res = multilevel = double_pass = None
     if not a.no_extra:
         log("[bench] policy paths")
         paths = policy_paths(nks, torch, ctx, gold, max(2, a.steps // 2))
         log("[bench] overlap operator")
         overlap_res = overlap_path(nks, torch, ctx, gold, a.steps)
+        log("[bench] multi-level nesting")
+        multilevel = multilevel_path(nks, torch, ctx, gold, a.steps)
+        log("[bench] double-pass mode")
+        double_pass = double_pass_path(nks, torch, ctx, gold, a.steps, large=not a.no_large)
         log("[bench] uneven batch")
         uneven = uneven_batch(nks, torch, ctx, 2)
     large = None
@@ -430,6 +538,8 @@ def main():
                          "pipelined_groups_value": main_run["napps"] * a.steps / pipe_dt},
         "policy_paths": paths,
         "overlap": overlap_res,
+        "multilevel": multilevel,
+        "double_pass": double_pass,
         "uneven_batch": uneven,
         "stencil_large": large,
         "tuning": main_run["tuned"],

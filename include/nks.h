@@ -123,6 +123,13 @@ typedef struct nks_opts {
  * b_m = b - sum_i <l_i, b> r_i and adds sum_i sgn(Re lambda_i) <l_i, b> r_i.
  * NKS_E_INVALID if the lattice has none. */
 #define NKS_FLAG_DEFLATE 2u
+/* flags: double-pass low-memory mode (Sec. 4.4).  The outer pass keeps only
+ * the two newest basis vectors; after the nested step the basis is built a
+ * second time from b (the same kernels, bit for bit the same vectors) and
+ * summed with the lift weights on the way.  Memory per job O(n) instead of
+ * O(n k) (see nks_workspace_size), at twice the outer-pass cost; results are
+ * identical to the single-pass ones bit for bit. */
+#define NKS_FLAG_DOUBLE_PASS 4u
 
 /* Per-result report (filled after the stream completes). */
 typedef struct nks_stats {
@@ -136,7 +143,8 @@ typedef struct nks_stats {
     int breakdown_iter;   /* iteration of a serious breakdown, else 0 */
     double inner_delta;   /* last ell-doubling relative change (policies), else 0 */
     double outer_delta;   /* last k-checkpoint relative change (policies), else 0 */
-    float ms_outer, ms_nested, ms_lift;  /* device time per phase (single-job calls) */
+    float ms_outer, ms_nested, ms_lift;  /* device time per phase (single-job calls; ms_lift
+                                            includes the second pass of NKS_FLAG_DOUBLE_PASS) */
     int levels_used;      /* nested levels that ran (0 = non-nested; < opts.levels when a
                              level was exact or the result came from a smaller setting) */
     int ell_deep_used[NKS_MAX_LEVELS - 1];   /* k_{i+2} built at the deeper levels */

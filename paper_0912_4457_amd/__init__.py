@@ -144,14 +144,16 @@ def _stream():
 
 FLAG_OVERLAP = 1
 FLAG_DEFLATE = 2
+FLAG_DOUBLE_PASS = 4
 
 
 def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50, rhi_tol=1e-14,
               k_policy=POLICY_FIXED, ell_policy=POLICY_FIXED, overlap=False, deflate=False,
-              ell_deep=(), p_deep=None) -> Opts:
+              ell_deep=(), p_deep=None, double_pass=False) -> Opts:
     """Options of one sign application.  ``ell_deep`` = sizes k_2, k_3, ...
     of the deeper nested levels (Sec. 4.5; k_1 = ell), ``p_deep`` their p
-    (None or <= 0: estimated)."""
+    (None or <= 0: estimated).  ``double_pass``: the low-memory mode of
+    Sec. 4.4 (two stored basis vectors, the basis built twice)."""
     o = Opts()
     lib().nks_opts_default(ctypes.byref(o))
     o.k, o.ell, o.tol = int(k), int(ell), float(tol)
@@ -159,7 +161,8 @@ def make_opts(k=200, ell=50, tol=1e-8, precision="fp64", p=None, max_rhi_iter=50
     o.p = 0.0 if p is None else float(p)
     o.max_rhi_iter, o.rhi_tol = int(max_rhi_iter), float(rhi_tol)
     o.k_policy, o.ell_policy = int(k_policy), int(ell_policy)
-    o.flags = (FLAG_OVERLAP if overlap else 0) | (FLAG_DEFLATE if deflate else 0)
+    o.flags = ((FLAG_OVERLAP if overlap else 0) | (FLAG_DEFLATE if deflate else 0)
+               | (FLAG_DOUBLE_PASS if double_pass else 0))
     ell_deep = list(ell_deep or ())
     if len(ell_deep) > MAX_LEVELS - 1:
         raise ValueError(f"at most {MAX_LEVELS - 1} deeper levels")
@@ -371,7 +374,8 @@ def sign_apply_batch(jobs, stats: bool = True):
                       precision=j.get("precision", "fp64"), p=j.get("p"),
                       k_policy=j.get("k_policy", POLICY_FIXED), ell_policy=j.get("ell_policy", POLICY_FIXED),
                       overlap=j.get("overlap", False), deflate=j.get("deflate", False),
-                      ell_deep=j.get("ell_deep", ()), p_deep=j.get("p_deep"))
+                      ell_deep=j.get("ell_deep", ()), p_deep=j.get("p_deep"),
+                      double_pass=j.get("double_pass", False))
         spec.append((lat, b, x, o))
         xs.append(x)
     ctx = spec[0][0].ctx

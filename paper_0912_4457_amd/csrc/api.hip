@@ -118,11 +118,12 @@ struct JobPlan {
     int group;          // index of its (lattice, precision) group
     int overlap;        // NKS_FLAG_OVERLAP
     int dm;             // deflated eigenpairs (NKS_FLAG_DEFLATE)
+    int ring;           // NKS_FLAG_DOUBLE_PASS: two-column store, second pass
     int levels;         // nested levels (multi-level nesting)
     int ell_deep[NKS_MAX_LEVELS - 1];
     double p_deep[NKS_MAX_LEVELS - 1];
     size_t off_dcoef, off_dpart;
-    size_t off_vstore, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
+    size_t off_vstore, off_yacc, off_lring, off_part, off_sc, off_status, off_report, off_omega, off_ckpt, off_label, off_nest,
         end;
     bool learned() const { return k_policy == NKS_POLICY_LEARNED || ell_policy == NKS_POLICY_LEARNED; }
 };
@@ -168,7 +169,8 @@ int validate_opts(nks_ctx* ctx, const nks_opts* o) {
         return fail(ctx, NKS_E_INVALID, "unknown policy");
     if ((o->k_policy == NKS_POLICY_LEARNED || o->ell_policy == NKS_POLICY_LEARNED) && !(ctx && ctx->net))
         return fail(ctx, NKS_E_UNSUPPORTED, "learned policy needs a network (nks_policy_load)");
-    if (o->flags & ~(unsigned)(NKS_FLAG_OVERLAP | NKS_FLAG_DEFLATE)) return fail(ctx, NKS_E_INVALID, "unknown flag bits");
+    if (o->flags & ~(unsigned)(NKS_FLAG_OVERLAP | NKS_FLAG_DEFLATE | NKS_FLAG_DOUBLE_PASS))
+        return fail(ctx, NKS_E_INVALID, "unknown flag bits");
     if ((o->k_policy != NKS_POLICY_FIXED || o->ell_policy != NKS_POLICY_FIXED) && !(o->tol > 0.0 && o->tol < 1.0))
         return fail(ctx, NKS_E_INVALID, "policies need 0 < tol < 1");
     if (o->levels < 1 || o->levels > NKS_MAX_LEVELS) return fail(ctx, NKS_E_INVALID, "levels must be in 1..NKS_MAX_LEVELS");
@@ -204,6 +206,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.tol = J.opts->tol;
         jp.label = label;
         jp.overlap = (J.opts->flags & NKS_FLAG_OVERLAP) ? 1 : 0;
+        jp.ring = (J.opts->flags & NKS_FLAG_DOUBLE_PASS) ? 1 : 0;
         set_levels(jp.levels, jp.ell_deep, jp.p_deep, J.opts);
         jp.dm = 0;
         if (J.opts->flags & NKS_FLAG_DEFLATE) {
@@ -240,7 +243,8 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
     for (auto& jp : P.jobs) {
         const size_t n = (size_t)12 * jp.lat->g.V;
         const size_t es = jp.precision == NKS_FP64 ? sizeof(double2) : sizeof(float2);
-        jp.off_vstore = off; off = align_up(off + (size_t)jp.k * n * es);
+        jp.off_vstore = off; off = align_up(off + (size_t)(jp.ring ? 2 : jp.k) * n * es);
+        jp.off_yacc = off; off = align_up(off + (jp.ring ? 2 * n * sizeof(double2) : 0));
         jp.off_lring = off; off = align_up(off + (jp.two_sided ? 2 * n * es : 0));
         jp.off_part = off; off = align_up(off + sizeof(double2) * PS_COUNT * jp.nblocks);
         jp.off_sc = off; off = align_up(off + sizeof(double2) * SC_COUNT * (jp.k + 2));
@@ -265,6 +269,8 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.b = static_cast<const double2*>(b);
     d.x = static_cast<double2*>(x);
     d.vstore = ws + jp.off_vstore;
+    d.ring = jp.ring;
+    d.yacc = jp.ring ? reinterpret_cast<double2*>(ws + jp.off_yacc) : nullptr;
     d.lring = jp.two_sided ? ws + jp.off_lring : nullptr;
     d.part = reinterpret_cast<double2*>(ws + jp.off_part);
     d.sc = reinterpret_cast<double2*>(ws + jp.off_sc);
@@ -321,9 +327,12 @@ OuterLaunch group_launch(const nks_ctx* ctx, const Plan& P, int gi, JobDesc* tab
     L.njobs = count;
     L.kmax = 0;
     L.deflate = 0;
+    L.ring = 0;
+    L.pass2 = 0;
     for (int i = start; i < start + count; ++i) {
         L.kmax = std::max(L.kmax, P.jobs[i].k);
         if (P.jobs[i].dm > 0) L.deflate = 1;
+        if (P.jobs[i].ring) L.ring = 1;
     }
     L.nblocks = jp.nblocks;
     L.precision = jp.precision;
@@ -376,8 +385,21 @@ double bytes_R(const OuterLaunch& L, const Plan& P, int start, int j) {
 double bytes_lift(const OuterLaunch& L, const Plan& P, int start) {
     const double cs = L.precision == NKS_FP64 ? 16.0 : 8.0;
     double per_site = 0.0;
-    for (int i = start; i < start + L.njobs; ++i) per_site += 12.0 * cs * P.jobs[i].k + 12.0 * 16.0;
+    for (int i = start; i < start + L.njobs; ++i)
+        per_site += (P.jobs[i].ring ? 2.0 * 12.0 * 16.0 : 12.0 * cs * P.jobs[i].k) + 12.0 * 16.0;
     return per_site * L.g.V;
+}
+
+// Double-pass jobs of a group: pack again and regenerate the basis, summing
+// omega_j u_j on the way (Sec. 4.4).  The nested step must have run.
+void enqueue_second_pass(OuterLaunch L, hipStream_t s) {
+    if (!L.ring) return;
+    L.pass2 = 1;
+    launch_pack(L, s);
+    for (int j = 1; j <= L.kmax; ++j) {
+        launch_outer_S(L, j, s);
+        if (j < L.kmax) launch_outer_R(L, j, s);
+    }
 }
 
 enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1, PH_LABEL = 2 };
@@ -466,6 +488,7 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
             ctx->prof_count[NKS_K_NESTED] = c + 1;
             launch_nested(L.jobs, L.njobs, s);
             prof_end(ctx, r, s);
+            enqueue_second_pass(L, s);
             const long long c2 = ctx->prof_count[NKS_K_LIFT];
             ctx->prof_count[NKS_K_LIFT] = 0;
             r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, start) : 0.0, s);
@@ -503,6 +526,7 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
     for (size_t gi = 0; gi < ng; ++gi) {
         hipStream_t sl = group_stream(ctx, gi, ng, s0);
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
+        enqueue_second_pass(L, sl);
         const long long c = ctx->prof_count[NKS_K_LIFT];
         ctx->prof_count[NKS_K_LIFT] = 0;
         int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, sl);

@@ -160,6 +160,11 @@ struct JobDesc {
     int levels;
     int ell_deep[NKS_MAX_LEVELS - 1];
     double p_deep[NKS_MAX_LEVELS - 1];
+    // double-pass mode (Sec. 4.4): the store holds two columns (u_j in column
+    // (j - 1) & 1); the second pass regenerates the basis and sums
+    // omega_j u_j into yacc, two SoA complex128 vectors (odd / even j)
+    int ring;
+    double2* yacc;
 };
 static_assert(ST_ELL_DEEP + NKS_MAX_LEVELS - 1 <= ST_COUNT && RP_P_DEEP + NKS_MAX_LEVELS - 1 <= RP_COUNT,
               "status / report words of the deeper levels");
@@ -253,6 +258,8 @@ struct OuterLaunch {
     int two_sided;
     Tuning tune;
     int deflate;           // some job of the group is deflated
+    int ring;              // some job of the group runs in double-pass mode
+    int pass2;             // 1: the second (regenerating) pass of those jobs
 };
 constexpr int OUTER_NT = 128;
 void launch_pack(const OuterLaunch& L, hipStream_t s);

@@ -15,6 +15,13 @@
 // Every block of S_{j+1} sums R_j's partials in the same order, so all blocks
 // agree on beta_j (and on a breakdown) without a grid barrier; block 0 stores
 // the scalars for the nested step.  All scalars stay on the device.
+//
+// Double-pass mode (Sec. 4.4): the store keeps only u_j and u_{j+1} (two
+// columns; r overwrites u_{j-1} at its own site, after reading it).  After
+// the nested step the same kernels run again from b (pass2 = 1): every sum
+// is taken in a fixed order, so they regenerate u_1 .. u_k bit for bit, and
+// S_j adds omega_j u_j to one of two accumulators (odd / even j, the
+// summation order of the lift).
 #include "wilson.h"
 
 namespace nks {
@@ -30,7 +37,22 @@ __device__ inline double2* slot(const JobDesc& J, int s) { return J.sc + (size_t
 
 template <typename R>
 __device__ inline cx_t<R>* column(const JobDesc& J, int j, int n) {   // j is 1-based
-    return reinterpret_cast<cx_t<R>*>(J.vstore) + (size_t)(j - 1) * n;
+    return reinterpret_cast<cx_t<R>*>(J.vstore) + (size_t)(J.ring ? ((j - 1) & 1) : (j - 1)) * n;
+}
+
+// Second pass: a job takes part only in double-pass mode, up to its final k.
+__device__ inline bool skip_S(const JobDesc& J, int j, int pass2) {
+    return pass2 ? (!J.ring || j > J.status[ST_KUSED]) : (j > J.k || J.status[ST_DONE]);
+}
+__device__ inline bool skip_R(const JobDesc& J, int j, int pass2) {
+    return pass2 ? (!J.ring || j >= J.status[ST_KUSED]) : (j >= J.k || J.status[ST_DONE]);
+}
+
+// Second pass, S_j: accumulator (j - 1) & 1 += omega_j u_j at element e.
+__device__ inline void accumulate(const JobDesc& J, int j, size_t e, int n, double2 u) {
+    double2* y = J.yacc + (size_t)((j - 1) & 1) * n + e;
+    const double2 prev = (j <= 2) ? mk(0.0, 0.0) : *y;
+    *y = cadd(prev, cmul(J.omega[j - 1], u));
 }
 
 template <typename R>
@@ -85,17 +107,18 @@ __global__ __launch_bounds__(NT) void deflate_dots_kernel(JobDesc* jobs, int V, 
 
 // ------------------------------------------------------------------ pack
 template <typename R>
-__global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblocks) {
+__global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblocks, int pass2) {
     const JobDesc& J = jobs[blockIdx.y];
+    if (pass2 && !J.ring) return;
     __shared__ double2 lds[NT / 64];
     const int site = blockIdx.x * NT + threadIdx.x;
     const int n = 12 * V;
-    if (blockIdx.x == 0 && threadIdx.x < ST_COUNT) {
+    if (!pass2 && blockIdx.x == 0 && threadIdx.x < ST_COUNT) {
         int v = 0;
         if (threadIdx.x == ST_KUSED) v = J.k;
         J.status[threadIdx.x] = v;
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < GROUP_WORDS && J.group) J.group[threadIdx.x] = 0;
+    if (!pass2 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < GROUP_WORDS && J.group) J.group[threadIdx.x] = 0;
     // deflation (App. C step 1): b_m = b - sum_i <l_i, b> r_i, with the
     // <l_i, b> re-reduced from deflate_dots' per-block partials by every block
     __shared__ double2 dco[DEFL_MAX];
@@ -133,11 +156,12 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
 // more resident waves hide more memory latency, at the price of spills.
 template <typename R, int MINW>
 __global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
-                                                  double kappa, int j, int nblocks, int njobs, int xcd_map) {
+                                                  double kappa, int j, int nblocks, int njobs, int xcd_map,
+                                                  int pass2) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
-    if (j > J.k || J.status[ST_DONE]) return;
+    if (skip_S(J, j, pass2)) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
     const bool b0 = (sb == 0 && threadIdx.x == 0);
@@ -189,6 +213,7 @@ __global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const 
             const double2 rd = to_d2<R>(rs);
             const double2 u = to_d2<R>(uj[e]);
             part += u.x * rd.x + u.y * rd.y;                          // Re(conj(u_j) r)
+            if (pass2) accumulate(J, j, e, n, u);
         }
     }
     const double2 s = block_sum<NT>(mk(part, 0.0), lds);
@@ -196,11 +221,12 @@ __global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const 
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map) {
+__global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map,
+                                             int pass2) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
-    if (j >= J.k || J.status[ST_DONE]) return;
+    if (skip_R(J, j, pass2)) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * V;
     const double svj = slot(J, SC_SV)[j].x;
@@ -232,11 +258,11 @@ __global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nb
 template <typename R, bool SPLIT, int MINW>
 __global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx_t<R>* __restrict__ links,
                                                 double kappa, double mu, int j, int nblocks, int njobs,
-                                                int xcd_map) {
+                                                int xcd_map, int pass2) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
-    if (j > J.k || J.status[ST_DONE]) return;
+    if (skip_S(J, j, pass2)) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
     const int field = SPLIT ? (int)blockIdx.z : 0;
@@ -312,6 +338,7 @@ __global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx
                     l = csub(l, cmul(cw, to_d2<R>(tl[e])));
                 }
                 const cx_t<R> rs = from_d2<R>(r);
+                if (pass2) accumulate(J, j, e, n, to_d2<R>(uj[e]));
                 if (rout) { rout[e] = rs; tl[e] = from_d2<R>(l); }
                 part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
             }
@@ -328,6 +355,7 @@ __global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx
                     double2 r = cmul(sv, to_d2<R>(acc[0][c]));
                     if (up) r = csub(r, cmul(cv, to_d2<R>(up[e])));
                     const cx_t<R> rs = from_d2<R>(r);
+                    if (pass2) accumulate(J, j, e, n, to_d2<R>(uj[e]));
                     if (rout) rout[e] = rs;
                     part = cadd(part, cmulc(to_d2<R>(tj[e]), to_d2<R>(rs)));   // conj(t_j) r
                 }
@@ -349,11 +377,12 @@ __global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx
 }
 
 template <typename R>
-__global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map) {
+__global__ __launch_bounds__(NT) void bi_R(JobDesc* jobs, int V, int j, int nblocks, int njobs, int xcd_map,
+                                           int pass2) {
     int sb, job;
     if (!block_coords(nblocks, njobs, xcd_map, sb, job)) return;
     const JobDesc& J = jobs[job];
-    if (j >= J.k || J.status[ST_DONE]) return;
+    if (skip_R(J, j, pass2)) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * V;
     const double2 sv = slot(J, SC_SV)[j], sw = slot(J, SC_SW)[j];
@@ -402,15 +431,21 @@ __global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
     const int c = e / V, s = e - c * V;
     const int kused = J.status[ST_KUSED];
     double2 acc0 = mk(0.0, 0.0), acc1 = mk(0.0, 0.0);
-    const cx_t<R>* base = reinterpret_cast<const cx_t<R>*>(J.vstore) + e;
-    int jj = 0;
-    for (; jj + 1 < kused; jj += 2) {
-        const double2 a = to_d2<R>(base[(size_t)jj * n]);
-        const double2 b = to_d2<R>(base[(size_t)(jj + 1) * n]);
-        acc0 = cadd(acc0, cmul(J.omega[jj], a));
-        acc1 = cadd(acc1, cmul(J.omega[jj + 1], b));
+    if (J.ring) {
+        // double-pass mode: the second pass has summed the basis already
+        if (kused >= 1) acc0 = J.yacc[e];
+        if (kused >= 2) acc1 = J.yacc[(size_t)n + e];
+    } else {
+        const cx_t<R>* base = reinterpret_cast<const cx_t<R>*>(J.vstore) + e;
+        int jj = 0;
+        for (; jj + 1 < kused; jj += 2) {
+            const double2 a = to_d2<R>(base[(size_t)jj * n]);
+            const double2 b = to_d2<R>(base[(size_t)(jj + 1) * n]);
+            acc0 = cadd(acc0, cmul(J.omega[jj], a));
+            acc1 = cadd(acc1, cmul(J.omega[jj + 1], b));
+        }
+        if (jj < kused) acc0 = cadd(acc0, cmul(J.omega[jj], to_d2<R>(base[(size_t)jj * n])));
     }
-    if (jj < kused) acc0 = cadd(acc0, cmul(J.omega[jj], to_d2<R>(base[(size_t)jj * n])));
     double2 y = cadd(acc0, acc1);
     // deflation (App. C step 6): + sum_i sgn(lambda_i) <l_i, b> r_i
     for (int i = 0; i < J.dm; ++i) y = cadd(y, cscale(cmul(J.dcoef[i], J.dr[(size_t)i * n + e]), J.dsgn[i]));
@@ -426,11 +461,11 @@ __global__ __launch_bounds__(LIFT_NT) void lift_kernel(JobDesc* jobs, int V) {
 
 void launch_pack(const OuterLaunch& L, hipStream_t s) {
     dim3 grid(L.nblocks, L.njobs);
-    if (L.deflate) hipLaunchKernelGGL(deflate_dots_kernel, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
+    if (L.deflate && !L.pass2) hipLaunchKernelGGL(deflate_dots_kernel, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
     if (L.precision == NKS_FP64)
-        hipLaunchKernelGGL(pack_kernel<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
+        hipLaunchKernelGGL(pack_kernel<double>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks, L.pass2);
     else
-        hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks);
+        hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks, L.pass2);
 }
 
 static dim3 outer_grid(const OuterLaunch& L, int z) {
@@ -447,13 +482,13 @@ static void outer_S_w(const OuterLaunch& L, int j, hipStream_t s) {
     const int xm = L.tune.xcd_map;
     if (!L.two_sided) {
         hipLaunchKernelGGL((herm_S<R, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j,
-                           L.nblocks, L.njobs, xm);
+                           L.nblocks, L.njobs, xm, L.pass2);
     } else if (L.tune.split_dual) {
         hipLaunchKernelGGL((bi_S<R, true, MINW>), outer_grid(L, 2), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
-                           L.mu, j, L.nblocks, L.njobs, xm);
+                           L.mu, j, L.nblocks, L.njobs, xm, L.pass2);
     } else {
         hipLaunchKernelGGL((bi_S<R, false, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
-                           L.mu, j, L.nblocks, L.njobs, xm);
+                           L.mu, j, L.nblocks, L.njobs, xm, L.pass2);
     }
 }
 
@@ -470,9 +505,11 @@ template <typename R>
 static void outer_R(const OuterLaunch& L, int j, hipStream_t s) {
     const int xm = L.tune.xcd_map;
     if (!L.two_sided)
-        hipLaunchKernelGGL(herm_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm);
+        hipLaunchKernelGGL(herm_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm,
+                           L.pass2);
     else
-        hipLaunchKernelGGL(bi_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm);
+        hipLaunchKernelGGL(bi_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm,
+                           L.pass2);
 }
 
 void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s) {

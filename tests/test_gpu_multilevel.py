@@ -60,6 +60,34 @@ def test_nested_step_levels_match_oracle_at_given_p(mu, depth):
     assert rel(c, c_ref) <= _sensitivity_tol(kr, herm, sizes, info["p"], c_ref)
 
 
+@functools.lru_cache(maxsize=None)
+def ritz_10x4_point(mu):
+    # H_500 of the 10^4 benchmark lattice (eps = 0.35) from a point source
+    from oracle import dirac, krylov
+    dims = (10, 10, 10, 10)
+    op = dirac.Operator(I.su3_links(dims, 0.35, 10401), dims, 1.6, mu)
+    b = I.point_source(dims, 0, 0).ravel()
+    if mu == 0.0:
+        return krylov.lanczos(op.matvec, b, 500)
+    return krylov.two_sided_lanczos(op.matvec, op.rmatvec, b, 500)
+
+
+# two-sided levels whose Ritz values spread beyond the level above (z_max
+# 3.1 -> 6.9 at the third level): 64 -> 20 -> 8 -> 4 -> 2 stays at 3e-6 in
+# the oracle, 64 -> 32 -> 16 -> 8 -> 4 reaches 3e-10; the GPU follows the
+# oracle in both regimes at the same p
+@pytest.mark.parametrize("sizes", [[64, 20, 8, 4, 2], [64, 32, 16, 8, 4]])
+def test_nested_step_levels_on_the_benchmark_H_k(sizes):
+    import paper_0912_4457_amd as nks
+    from oracle import multilevel
+    kr = ritz_10x4_point(0.2)
+    c_ref, info = multilevel.multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, False, sizes)
+    c, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, False, sizes[0], p=info["p"][0],
+                            ell_deep=sizes[1:], p_deep=info["p"][1:])
+    assert st["status"] == 0 and st["levels_used"] == len(sizes)
+    assert rel(c, c_ref) <= _sensitivity_tol(kr, False, sizes, info["p"], c_ref)
+
+
 def test_nested_step_levels_estimate_p_like_the_oracle():
     # Hermitian levels: Sturm multisection finds the same Ritz extremes as the
     # oracle's eigensolver, so every p and the result agree closely
