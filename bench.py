@@ -36,6 +36,7 @@ DIMS = (10, 10, 10, 10)
 EPS, LINK_SEED, M0 = 0.35, 10401, 1.6
 MUS = (0.0, 0.2)
 K, ELL = 500, 64
+INFLIGHT = 2          # batches in flight on separate streams in the timed region
 SERIAL_GROUPS = False    # --serial-groups
 KERNEL_SOURCES = ("paper_0912_4457_amd/csrc/wilson.h", "paper_0912_4457_amd/csrc/outer.hip")
 
@@ -117,6 +118,30 @@ def errors_vs_golden(jobs, xs, gold):
     return errs
 
 
+def inflight_slots(nks, torch, jobs, n):
+    """n independent copies of a batch (own outputs, workspace and stream), so
+    that consecutive steps can be in flight together: while one batch runs
+    its nested step (one workgroup per job) the next one's outer passes fill
+    the rest of the GPU."""
+    slots = []
+    size = nks.workspace_size([(j["lat"], j["b"], j["x"], nks.make_opts(k=j["k"], ell=j["ell"],
+                                                                          precision=j["precision"]))
+                               for j in jobs])
+    for i in range(n):
+        js = jobs if i == 0 else [dict(j, x=torch.empty_like(j["b"])) for j in jobs]
+        ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+        st = torch.cuda.Stream()
+        slots.append((js, ws, st))
+    return slots
+
+
+def run_slots(nks, torch, slots, steps):
+    for s in range(steps):
+        js, ws, st = slots[s % len(slots)]
+        with torch.cuda.stream(st):
+            nks.sign_apply_batch(js, stats=False, workspace=ws)
+
+
 def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True):
     lats, jobs = make_jobs(nks, torch, ctx, precision)
     tuned = None
@@ -124,16 +149,21 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
         from paper_0912_4457_amd.autotune import autotune
         tuned = autotune(ctx, jobs, use_cache=False)
         log(f"[bench] autotune {precision}: {tuned['choice']} {tuned['timings']}")
-    for _ in range(warmup):
-        xs, sts = nks.sign_apply_batch(jobs, stats=False)
+    slots = inflight_slots(nks, torch, jobs, INFLIGHT)
+    run_slots(nks, torch, slots, max(warmup, INFLIGHT))
     torch.cuda.synchronize()
     # timed region: the library's default path (graph replay, lattice groups
-    # on concurrent streams)
+    # on concurrent streams), consecutive steps in flight on INFLIGHT streams
     t0 = time.perf_counter()
-    for _ in range(steps):
-        xs, _ = nks.sign_apply_batch(jobs, stats=False)
+    run_slots(nks, torch, slots, steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    one_dt = None
+    if INFLIGHT > 1:
+        t1 = time.perf_counter()
+        run_slots(nks, torch, slots[:1], steps)
+        torch.cuda.synchronize()
+        one_dt = time.perf_counter() - t1
     prof = {}
     if profile:
         # per-kernel launch durations: the same steps again with the groups one
@@ -152,7 +182,13 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
     xs, sts = nks.sign_apply_batch(jobs, stats=True)   # one more call for the per-job report
     torch.cuda.synchronize()
     errs = errors_vs_golden(jobs, xs, gold)
-    return dict(seconds=dt, steps=steps, napps=len(jobs), prof=prof, stats=sts, errs=errs, tuned=tuned)
+    # every in-flight copy computed the same results
+    for js, _, _ in slots[1:]:
+        for a, b in zip(jobs, js):
+            if not torch.equal(a["x"], b["x"]):
+                raise RuntimeError("in-flight copies of the batch disagree")
+    return dict(seconds=dt, steps=steps, napps=len(jobs), prof=prof, stats=sts, errs=errs, tuned=tuned,
+                one_stream_seconds=one_dt)
 
 
 def time_calls(nks, torch, jobs, steps, warmup, graph=True):
@@ -514,7 +550,8 @@ def main():
         "data": "synthetic (seeded SU(3) links and point sources)",
         "config": {"workload": "point12_10x4: 10^4 lattice, 12 point sources x mu in {0, 0.2}, "
                                f"eps=0.35, m0=1.6, k={K}, ell={ELL}",
-                   "applications_per_step": main_run["napps"], "k": K, "ell": ELL},
+                   "applications_per_step": main_run["napps"], "k": K, "ell": ELL,
+                   "batches_in_flight": INFLIGHT},
         "roofline": {"bound": "hbm", "kernel": "outer stencil pass (A v fused with the recurrence terms)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
@@ -532,6 +569,9 @@ def main():
         "other_path": {"precision": other,
                        "value": other_run["napps"] * other_run["steps"] / other_run["seconds"],
                        "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None)},
+        "batches_in_flight": {"count": INFLIGHT, "value": value,
+                              "one_batch_at_a_time_value": (main_run["napps"] * a.steps / main_run["one_stream_seconds"]
+                                                            if main_run["one_stream_seconds"] else None)},
         "graph_replay": {"value": main_run["napps"] * a.steps / graph_dt,
                          "eager_value": main_run["napps"] * a.steps / eager_dt,
                          "groups_one_after_another_value": main_run["napps"] * a.steps / serial_dt,

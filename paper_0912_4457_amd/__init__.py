@@ -357,11 +357,14 @@ def sign_apply(lat: Lattice, b, k: int = 200, ell: int = 50, p: float | None = N
     return x, (st.as_dict() if stats else None)
 
 
-def sign_apply_batch(jobs, stats: bool = True):
+def sign_apply_batch(jobs, stats: bool = True, workspace=None):
     """jobs: list of dicts {lat, b, k, ell, p, precision} (or with 'x').
 
-    All jobs run in one call; jobs on the same lattice share each stencil
-    sweep.  Returns (list of x tensors, list of stats dicts or None)."""
+    All jobs run in one call on the current torch stream; jobs on the same
+    lattice share each stencil sweep.  ``workspace``: a device uint8 tensor
+    of at least nks_workspace_size bytes (default: the context's own), so
+    that batches can be in flight on several streams at once.  Returns (list
+    of x tensors, list of stats dicts or None)."""
     torch = _torch()
     spec = []
     xs = []
@@ -382,7 +385,12 @@ def sign_apply_batch(jobs, stats: bool = True):
     arr, keep = _job_array(spec)
     sz = ctypes.c_size_t()
     ctx.check(lib().nks_workspace_size(ctx.h, len(spec), arr, ctypes.byref(sz)))
-    ws = ctx.workspace(sz.value)
+    if workspace is None:
+        ws = ctx.workspace(sz.value)
+    else:
+        ws = workspace
+        if ws.dtype != torch.uint8 or not ws.is_cuda or ws.numel() < sz.value:
+            raise ValueError(f"workspace must be a device uint8 tensor of >= {sz.value} bytes")
     sts = (Stats * len(spec))()
     ctx.check(lib().nks_sign_apply_batch(ctx.h, len(spec), arr, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                          _stream(), sts if stats else None))
