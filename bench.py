@@ -36,7 +36,7 @@ DIMS = (10, 10, 10, 10)
 EPS, LINK_SEED, M0 = 0.35, 10401, 1.6
 MUS = (0.0, 0.2)
 K, ELL = 500, 64
-INFLIGHT = 2          # batches in flight on separate streams in the timed region
+INFLIGHT = 1          # batches in flight on separate streams in the timed region
 SERIAL_GROUPS = False    # --serial-groups
 KERNEL_SOURCES = ("paper_0912_4457_amd/csrc/wilson.h", "paper_0912_4457_amd/csrc/outer.hip")
 

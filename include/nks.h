@@ -314,6 +314,8 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  * them after timing the alternatives):
  *   "xcd_map"    1: 1D grid that keeps every job of a site block on one XCD
  *                2: 1D grid that gives each XCD whole jobs (all site blocks)
+ *                3: 1D grid that gives each XCD half of the lattice (in t)
+ *                   for a quarter of the jobs
  *                0: 2D grid (site block, job)
  *   "split_dual" 1: the two-sided stencil computes A u and A^dagger t in
  *                separate workgroups; 0: one thread does both.

@@ -16,7 +16,7 @@ import itertools
 import json
 import os
 
-SPACE = {"xcd_map": (0, 1, 2), "split_dual": (0, 1), "min_waves": (1, 3, 4)}
+SPACE = {"xcd_map": (0, 1, 2, 3), "split_dual": (0, 1), "min_waves": (1, 3, 4)}
 
 
 def _cache_path() -> str:

@@ -666,7 +666,7 @@ int nks_create(int device, nks_ctx** out) {
     if (hipSetDevice(device) != hipSuccess) return NKS_E_HIP;
     auto* c = new nks_ctx();
     c->device = device;
-    if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = std::min(2, std::max(0, atoi(e)));
+    if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = std::min(3, std::max(0, atoi(e)));
     if (const char* e = getenv("NKS_SPLIT_DUAL")) c->tune.split_dual = atoi(e) != 0;
     if (const char* e = getenv("NKS_GRAPH")) c->graph = atoi(e) != 0;
     for (auto& e : c->ev)
@@ -1077,7 +1077,7 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
     if (!ctx || !key) return NKS_E_INVALID;
     const std::string k(key);
     if (k == "xcd_map") {
-        if (value < 0 || value > 2) return fail(ctx, NKS_E_INVALID, "xcd_map takes 0, 1 or 2");
+        if (value < 0 || value > 3) return fail(ctx, NKS_E_INVALID, "xcd_map takes 0, 1, 2 or 3");
         ctx->tune.xcd_map = value;
     } else if (k == "split_dual") ctx->tune.split_dual = value != 0;
     else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;

@@ -262,6 +262,45 @@ struct OuterLaunch {
     int pass2;             // 1: the second (regenerating) pass of those jobs
 };
 constexpr int OUTER_NT = 128;
+
+// Launch map of the outer passes (tuning key xcd_map).  The hardware hands
+// workgroup b of a 1D grid to XCD b % 8, so b -> (site block, job) decides
+// which part of the (site block, job) rectangle each XCD's L2 serves:
+//   1: a contiguous eighth of the site blocks, all jobs (jobs innermost);
+//   2: a contiguous eighth of the (job, site block) pairs, job-major;
+//   3: half of the site blocks (a contiguous half in t) for a quarter of the
+//      jobs: each XCD fetches a t-halo of two slices per half lattice
+//      instead of per eighth, and the links of its half for its jobs.
+// xcd_slots is the number of workgroups per XCD (grid = 8 * slots);
+// map_block returns false for padding workgroups.
+__host__ __device__ inline int xcd_slots(int nblocks, int njobs, int xcd_map) {
+    if (xcd_map == 3) return ((nblocks + 1) / 2) * ((njobs + 3) / 4);
+    return (nblocks * njobs + 7) / 8;
+}
+__host__ __device__ inline bool map_block(int b, int nblocks, int njobs, int xcd_map, int& sb, int& job) {
+    const int x = b & 7, i = b >> 3;
+    if (xcd_map == 3) {
+        const int tp = x & 1, jp = x >> 1;
+        const int sb_lo = tp * nblocks / 2, sb_hi = (tp + 1) * nblocks / 2;
+        const int j_lo = jp * njobs / 4, j_hi = (jp + 1) * njobs / 4;
+        const int m = j_hi - j_lo;
+        if (m <= 0 || i >= (sb_hi - sb_lo) * m) return false;
+        sb = sb_lo + i / m;
+        job = j_lo + i % m;
+        return true;
+    }
+    const int total = nblocks * njobs;
+    const int q = x * xcd_slots(nblocks, njobs, xcd_map) + i;
+    if (q >= total) return false;
+    if (xcd_map == 2) {
+        job = q / nblocks;
+        sb = q - job * nblocks;
+    } else {
+        sb = q / njobs;
+        job = q - sb * njobs;
+    }
+    return true;
+}
 void launch_pack(const OuterLaunch& L, hipStream_t s);
 void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s);   // stencil pass of iteration j
 void launch_outer_R(const OuterLaunch& L, int j, hipStream_t s);   // recurrence pass (j < k only)

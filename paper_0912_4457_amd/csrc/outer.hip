@@ -60,29 +60,11 @@ __device__ inline cx_t<R>* lvec(const JobDesc& J, int j, int n) {     // t_j in 
     return reinterpret_cast<cx_t<R>*>(J.lring) + (size_t)(j & 1) * n;
 }
 
-// Block -> (site block, job).  With xcd_map the grid is 1D and padded to a
-// multiple of 8; the hardware hands workgroup b to XCD b % 8, so giving each
-// XCD a contiguous range of (site block, job) pairs, jobs innermost, keeps a
-// site block's links and neighbour spinors in one XCD's L2 while all jobs
-// sweep it.  Returns false for padding blocks.
-// xcd_map == 2 orders the pairs job-major instead: every XCD sweeps the whole
-// lattice for its own share of the jobs, so the neighbour spinors of its jobs
-// stay in its L2 and only the links (shared by all jobs) are read by every XCD.
+// Block -> (site block, job): the 2D grid (xcd_map 0) or the XCD-aware 1D
+// maps of map_block.  Returns false for padding blocks.
 __device__ inline bool block_coords(int nblocks, int njobs, int xcd_map, int& sb, int& job) {
     if (!xcd_map) { sb = blockIdx.x; job = blockIdx.y; return true; }
-    const int total = nblocks * njobs;
-    const int per = (total + 7) / 8;
-    const int b = blockIdx.x;
-    const int q = (b & 7) * per + (b >> 3);
-    if (q >= total) return false;
-    if (xcd_map == 2) {
-        job = q / nblocks;
-        sb = q - job * nblocks;
-    } else {
-        sb = q / njobs;
-        job = q - sb * njobs;
-    }
-    return true;
+    return map_block(blockIdx.x, nblocks, njobs, xcd_map, sb, job);
 }
 
 // ------------------------------------------------------------------ deflation dots
@@ -469,10 +451,7 @@ void launch_pack(const OuterLaunch& L, hipStream_t s) {
 }
 
 static dim3 outer_grid(const OuterLaunch& L, int z) {
-    if (L.tune.xcd_map) {
-        const int total = L.nblocks * L.njobs;
-        return dim3(8 * ((total + 7) / 8), 1, z);
-    }
+    if (L.tune.xcd_map) return dim3(8 * xcd_slots(L.nblocks, L.njobs, L.tune.xcd_map), 1, z);
     return dim3(L.nblocks, L.njobs, z);
 }
 

@@ -123,7 +123,8 @@ def test_tuning_choices_are_bitwise_identical():
     ref = None
     try:
         for xm, sd, mw, cg in ((0, 0, 1, 1), (0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 1, 1), (2, 0, 1, 1),
-                               (2, 1, 1, 1), (1, 1, 3, 1), (1, 0, 4, 1), (1, 1, 4, 1), (1, 1, 1, 0)):
+                               (2, 1, 1, 1), (3, 0, 1, 1), (3, 1, 1, 1), (3, 1, 4, 0), (1, 1, 3, 1),
+                               (1, 0, 4, 1), (1, 1, 4, 1), (1, 1, 1, 0)):
             c.tune_set("xcd_map", xm)
             c.tune_set("split_dual", sd)
             c.tune_set("min_waves", mw)
@@ -152,7 +153,7 @@ def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
     jobs = [dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=40, ell=10)]
     res = autotune.autotune(c, jobs, k_probe=16)
     assert set(res["choice"]) == {"xcd_map", "split_dual", "min_waves"}
-    assert len(res["timings"]) == 18
+    assert len(res["timings"]) == 24
     assert c.tune_get("split_dual") == res["choice"]["split_dual"]
     again = autotune.autotune(c, jobs, k_probe=16)     # cached
     assert again["choice"] == res["choice"]
