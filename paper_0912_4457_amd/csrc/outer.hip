@@ -134,6 +134,40 @@ __global__ __launch_bounds__(NT) void pack_kernel(JobDesc* jobs, int V, int nblo
 }
 
 // ------------------------------------------------------------------ Hermitian step
+// Scalars of S_j from R_{j-1}'s partial sums: beta_{j-1} (|b| when j == 1),
+// v_j = svj u_j and beta_{j-1} v_{j-1} = cprev u_{j-1}; block 0 (b0) stores
+// them.  Returns false when the job stops here (zero source, invariant subspace).
+template <int NTB>
+__device__ inline bool herm_scalars(const JobDesc& J, int j, int nblocks, bool b0, double2* lds, double& svj,
+                                    double& cprev) {
+    const double beta = sqrt(sum_partials<NTB>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
+    if (j == 1) {
+        if (beta == 0.0) {                                  // zero source: x = 0
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
+            return false;
+        }
+        svj = 1.0 / beta;
+        cprev = 0.0;
+        if (b0) { J.report[RP_BNORM] = beta; slot(J, SC_SV)[1] = mk(svj, 0.0); slot(J, SC_VN)[1] = mk(1.0, 0.0); }
+        return true;
+    }
+    const double aprev = slot(J, SC_ALPHA)[j - 1].x;
+    const double bprev = (j >= 3) ? slot(J, SC_BETA)[j - 2].x : 0.0;
+    if (beta <= LUCKY_TAU_HERMITIAN * (fabs(aprev) + bprev)) {   // invariant subspace
+        if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
+        return false;
+    }
+    svj = 1.0 / beta;
+    cprev = beta * slot(J, SC_SV)[j - 1].x;                       // beta_{j-1} v_{j-1} = cprev u_{j-1}
+    if (b0) {
+        slot(J, SC_BETA)[j - 1] = mk(beta, 0.0);
+        slot(J, SC_GAMMA)[j - 1] = mk(beta, 0.0);
+        slot(J, SC_SV)[j] = mk(svj, 0.0);
+        slot(J, SC_VN)[j] = mk(1.0, 0.0);
+    }
+    return true;
+}
+
 // MINW: waves per SIMD the register allocation must allow (1 = no limit);
 // more resident waves hide more memory latency, at the price of spills.
 template <typename R, int MINW>
@@ -146,34 +180,8 @@ __global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const 
     if (skip_S(J, j, pass2)) return;
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
-    const bool b0 = (sb == 0 && threadIdx.x == 0);
-    // beta_{j-1} (or |b| when j == 1) from the previous kernel's partial sums
-    const double beta = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
     double svj, cprev;
-    if (j == 1) {
-        if (beta == 0.0) {                                  // zero source: x = 0
-            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
-            return;
-        }
-        svj = 1.0 / beta;
-        cprev = 0.0;
-        if (b0) { J.report[RP_BNORM] = beta; slot(J, SC_SV)[1] = mk(svj, 0.0); slot(J, SC_VN)[1] = mk(1.0, 0.0); }
-    } else {
-        const double aprev = slot(J, SC_ALPHA)[j - 1].x;
-        const double bprev = (j >= 3) ? slot(J, SC_BETA)[j - 2].x : 0.0;
-        if (beta <= LUCKY_TAU_HERMITIAN * (fabs(aprev) + bprev)) {   // invariant subspace
-            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
-            return;
-        }
-        svj = 1.0 / beta;
-        cprev = beta * slot(J, SC_SV)[j - 1].x;                       // beta_{j-1} v_{j-1} = cprev u_{j-1}
-        if (b0) {
-            slot(J, SC_BETA)[j - 1] = mk(beta, 0.0);
-            slot(J, SC_GAMMA)[j - 1] = mk(beta, 0.0);
-            slot(J, SC_SV)[j] = mk(svj, 0.0);
-            slot(J, SC_VN)[j] = mk(1.0, 0.0);
-        }
-    }
+    if (!herm_scalars<NT>(J, j, nblocks, sb == 0 && threadIdx.x == 0, lds, svj, cprev)) return;
     const int site = sb * NT + threadIdx.x;
     double part = 0.0;
     if (site < g.V) {
@@ -233,6 +241,61 @@ __global__ __launch_bounds__(NT) void herm_R(JobDesc* jobs, int V, int j, int nb
     if (threadIdx.x == 0) J.part[(size_t)PS_R0 * nblocks + sb] = s;
 }
 
+// Scalars of the two-sided S_j from R_{j-1}'s partial sums (App. B):
+// v_j = sv u_j, w_j = sw t_j, gamma_{j-1} v_{j-1} = cv u_{j-1},
+// conj(beta_{j-1}) w_{j-1} = cw t_{j-1}; block 0 (b0) stores them.  Returns
+// false when the job stops here (zero source, lucky or serious breakdown).
+template <int NTB>
+__device__ inline bool bi_scalars(const JobDesc& J, int j, int nblocks, bool b0, double2* lds, double2& sv,
+                                  double2& sw, double2& cv, double2& cw) {
+    if (j == 1) {
+        const double bn = sqrt(sum_partials<NTB>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
+        if (bn == 0.0) {
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
+            return false;
+        }
+        sv = sw = mk(1.0 / bn, 0.0);
+        cv = cw = mk(0.0, 0.0);
+        if (b0) {
+            J.report[RP_BNORM] = bn;
+            slot(J, SC_SV)[1] = sv; slot(J, SC_SW)[1] = sw;
+            slot(J, SC_VN)[1] = mk(1.0, 0.0); slot(J, SC_WN)[1] = mk(1.0, 0.0);
+        }
+    } else {
+        const double2 delta = sum_partials<NTB>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds);
+        const double nr = sqrt(sum_partials<NTB>(J.part + (size_t)PS_R1 * nblocks, nblocks, lds).x);
+        const double nl = sqrt(sum_partials<NTB>(J.part + (size_t)PS_R2 * nblocks, nblocks, lds).x);
+        const double aprev = cabs(slot(J, SC_ALPHA)[j - 1]);
+        const double sprev = (j >= 3) ? sqrt(cabs(cmul(slot(J, SC_BETA)[j - 2], slot(J, SC_GAMMA)[j - 2]))) : 0.0;
+        const double S = aprev + sprev;
+        if (nr <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_VN)[j - 1].x ||
+            nl <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_WN)[j - 1].x) {
+            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
+            return false;
+        }
+        if (cabs(delta) <= SERIOUS_TAU * nr * nl) {
+            if (b0) {
+                J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1;
+                J.status[ST_STATUS] = NKS_E_BREAKDOWN; J.status[ST_BDITER] = j - 1;
+            }
+            return false;
+        }
+        const double2 beta = csqrt_principal(delta);
+        const double2 gamma = cdiv(cconj(delta), beta);
+        sv = crecip(beta);
+        sw = crecip(cconj(gamma));
+        cv = cmul(gamma, slot(J, SC_SV)[j - 1]);              // gamma_{j-1} v_{j-1}
+        cw = cmul(cconj(beta), slot(J, SC_SW)[j - 1]);        // conj(beta_{j-1}) w_{j-1}
+        if (b0) {
+            slot(J, SC_BETA)[j - 1] = beta; slot(J, SC_GAMMA)[j - 1] = gamma;
+            slot(J, SC_SV)[j] = sv; slot(J, SC_SW)[j] = sw;
+            slot(J, SC_VN)[j] = mk(nr / cabs(beta), 0.0);
+            slot(J, SC_WN)[j] = mk(nl / cabs(gamma), 0.0);
+        }
+    }
+    return true;
+}
+
 // ------------------------------------------------------------------ two-sided step
 // SPLIT = false: one thread computes A u_j and A^dagger t_j (links loaded once).
 // SPLIT = true: blockIdx.z selects the field (0: A u_j, 1: A^dagger t_j), which
@@ -248,53 +311,8 @@ __global__ __launch_bounds__(NT, MINW) void bi_S(JobDesc* jobs, Geom g, const cx
     __shared__ double2 lds[NT / 64];
     const int n = 12 * g.V;
     const int field = SPLIT ? (int)blockIdx.z : 0;
-    const bool b0 = (sb == 0 && threadIdx.x == 0 && field == 0);
     double2 sv, sw, cv, cw;   // v_j = sv u_j, w_j = sw t_j; subtract cv u_{j-1}, cw t_{j-1}
-    if (j == 1) {
-        const double bn = sqrt(sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds).x);
-        if (bn == 0.0) {
-            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = 0; J.report[RP_BNORM] = 0.0; }
-            return;
-        }
-        sv = sw = mk(1.0 / bn, 0.0);
-        cv = cw = mk(0.0, 0.0);
-        if (b0) {
-            J.report[RP_BNORM] = bn;
-            slot(J, SC_SV)[1] = sv; slot(J, SC_SW)[1] = sw;
-            slot(J, SC_VN)[1] = mk(1.0, 0.0); slot(J, SC_WN)[1] = mk(1.0, 0.0);
-        }
-    } else {
-        const double2 delta = sum_partials<NT>(J.part + (size_t)PS_R0 * nblocks, nblocks, lds);
-        const double nr = sqrt(sum_partials<NT>(J.part + (size_t)PS_R1 * nblocks, nblocks, lds).x);
-        const double nl = sqrt(sum_partials<NT>(J.part + (size_t)PS_R2 * nblocks, nblocks, lds).x);
-        const double aprev = cabs(slot(J, SC_ALPHA)[j - 1]);
-        const double sprev = (j >= 3) ? sqrt(cabs(cmul(slot(J, SC_BETA)[j - 2], slot(J, SC_GAMMA)[j - 2]))) : 0.0;
-        const double S = aprev + sprev;
-        if (nr <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_VN)[j - 1].x ||
-            nl <= LUCKY_TAU_TWO_SIDED * S * slot(J, SC_WN)[j - 1].x) {
-            if (b0) { J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1; }
-            return;
-        }
-        if (cabs(delta) <= SERIOUS_TAU * nr * nl) {
-            if (b0) {
-                J.status[ST_DONE] = 1; J.status[ST_KUSED] = j - 1;
-                J.status[ST_STATUS] = NKS_E_BREAKDOWN; J.status[ST_BDITER] = j - 1;
-            }
-            return;
-        }
-        const double2 beta = csqrt_principal(delta);
-        const double2 gamma = cdiv(cconj(delta), beta);
-        sv = crecip(beta);
-        sw = crecip(cconj(gamma));
-        cv = cmul(gamma, slot(J, SC_SV)[j - 1]);              // gamma_{j-1} v_{j-1}
-        cw = cmul(cconj(beta), slot(J, SC_SW)[j - 1]);        // conj(beta_{j-1}) w_{j-1}
-        if (b0) {
-            slot(J, SC_BETA)[j - 1] = beta; slot(J, SC_GAMMA)[j - 1] = gamma;
-            slot(J, SC_SV)[j] = sv; slot(J, SC_SW)[j] = sw;
-            slot(J, SC_VN)[j] = mk(nr / cabs(beta), 0.0);
-            slot(J, SC_WN)[j] = mk(nl / cabs(gamma), 0.0);
-        }
-    }
+    if (!bi_scalars<NT>(J, j, nblocks, sb == 0 && threadIdx.x == 0 && field == 0, lds, sv, sw, cv, cw)) return;
     const int site = sb * NT + threadIdx.x;
     double2 part = mk(0.0, 0.0);
     if (site < g.V) {
