@@ -53,8 +53,13 @@ def source_hash(paths=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """Per-launch HBM bytes of the stencil pass from profiles/, if the kernel is unchanged."""
+def tuning_str(choice) -> str:
+    return ",".join(f"{k}={int(v)}" for k, v in sorted(choice.items()))
+
+
+def recorded_traffic(tuning=None):
+    """Per-launch HBM bytes of the stencil pass from profiles/, if the kernel is
+    unchanged and the counters were taken with the same launch tuning."""
     path = os.path.join(ROOT, "profiles", "stencil_point12_10x4_pmc.txt")
     if not os.path.exists(path):
         return None
@@ -64,6 +69,8 @@ def recorded_traffic():
             k_, v_ = line.split(":", 1)
             vals[k_.strip()] = v_.strip()
     if vals.get("source_sha") != source_hash():
+        return None
+    if tuning is not None and vals.get("tuning") != tuning_str(tuning):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -461,6 +468,7 @@ def main():
                          "per-launch durations must not include overlap)")
     ap.add_argument("--probe", action="store_true",
                     help="short run of the main path only (for hardware-counter passes)")
+    ap.add_argument("--tune", default="", help="launch tuning for --probe, e.g. xcd_map=3,split_dual=1,min_waves=1")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): jobs are independent "
@@ -483,11 +491,14 @@ def main():
     gold = golden_samples()
 
     if a.probe:
+        for kv in filter(None, a.tune.split(",")):
+            k_, v_ = kv.split("=")
+            ctx.tune_set(k_.strip(), int(v_))
         lats, jobs = make_jobs(nks, torch, ctx, a.precision)
         for _ in range(max(1, a.steps)):
             nks.sign_apply_batch(jobs, stats=False)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": True, "precision": a.precision, "calls": max(1, a.steps)}))
+        print(json.dumps({"probe": True, "precision": a.precision, "calls": max(1, a.steps), "tune": a.tune}))
         return
     log(f"[bench] {a.precision} path: 24 jobs per step, {a.warmup} warmup + {a.steps} timed steps")
     main_run = run_path(nks, torch, ctx, a.precision, a.steps, a.warmup, gold, profile=True)
@@ -533,7 +544,7 @@ def main():
     value = main_run["napps"] * a.steps / dt
     st = main_run["prof"]["stencil"]
     achieved = st["alg_bytes"] / (st["avg_ms"] * 1e-3) / 1e9
-    traffic = recorded_traffic()
+    traffic = recorded_traffic(main_run["tuned"]["choice"] if main_run["tuned"] else None)
     sts = main_run["stats"]
     out = {
         "metric": METRIC,

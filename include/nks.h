@@ -338,9 +338,12 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
 int nks_tune_set(nks_ctx* ctx, const char* key, int value);
 int nks_tune_get(nks_ctx* ctx, const char* key, int* value);
 
-/* Measurement support.  When enabled on a context, sign applications bracket
- * every 8th launch of each kernel class with HIP events on the call's stream
- * (sampling keeps the timing overhead negligible).  nks_profile_read waits
+/* Measurement support.  When enabled on a context, sign applications time
+ * every 8th launch of each kernel class (every nested and lift launch) with
+ * start/stop events that the launch's own dispatch stamps
+ * (hipExtLaunchKernelGGL), so a duration is the kernel's execution without
+ * the gaps between launches; profiled calls run eagerly (no graph replay).
+ * nks_profile_read waits
  * for those events, returns the number of timed launches, their summed
  * device time and their summed algorithmic bytes (what each launch must move
  * at minimum: inputs read once, outputs written once), and resets the class. */

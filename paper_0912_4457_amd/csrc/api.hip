@@ -344,21 +344,28 @@ OuterLaunch group_launch(const nks_ctx* ctx, const Plan& P, int gi, JobDesc* tab
 constexpr int PROF_EVERY = 8;     // time one launch in eight of each class
 constexpr size_t PROF_POOL = 4096;
 
-// Begin timing a launch of class cls if it is sampled; returns the record index or -1.
-int prof_begin(nks_ctx* ctx, int cls, double bytes, hipStream_t s) {
-    if (!ctx->prof) return -1;
-    if (ctx->prof_count[cls]++ % PROF_EVERY != 0) return -1;
-    if (ctx->pool.size() < 2) return -1;
+// Pick one launch in PROF_EVERY of class cls for timing; its events go to the
+// dispatch of that launch (LaunchEvents), which stamps the kernel's own start
+// and end.  Returns null events for launches that are not timed.
+LaunchEvents prof_take(nks_ctx* ctx, int cls, double bytes) {
+    if (!ctx->prof) return {};
+    if (ctx->prof_count[cls]++ % PROF_EVERY != 0) return {};
+    if (ctx->pool.size() < 2) return {};
     ProfRecord r{cls, ctx->pool.back(), nullptr, bytes};
     ctx->pool.pop_back();
     r.b = ctx->pool.back();
     ctx->pool.pop_back();
-    if (hipEventRecord(r.a, s) != hipSuccess) return -1;
     ctx->pending.push_back(r);
-    return (int)ctx->pending.size() - 1;
+    return {r.a, r.b};
 }
-void prof_end(nks_ctx* ctx, int rec, hipStream_t s) {
-    if (rec >= 0) (void)hipEventRecord(ctx->pending[rec].b, s);
+
+// The nested step and the lift are timed at every launch.
+LaunchEvents prof_take_always(nks_ctx* ctx, int cls, double bytes) {
+    const long long c = ctx->prof_count[cls];
+    ctx->prof_count[cls] = 0;
+    LaunchEvents ev = prof_take(ctx, cls, bytes);
+    ctx->prof_count[cls] = c + 1;
+    return ev;
 }
 
 // Algorithmic bytes of one launch: every input read once, every output written once.
@@ -467,13 +474,13 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
         }
         launch_pack(L, s);
         for (int j = 1; j <= L.kmax; ++j) {
-            int r = prof_begin(ctx, NKS_K_STENCIL, ctx->prof ? bytes_S(L, P, start, j) : 0.0, s);
+            L.ev = prof_take(ctx, NKS_K_STENCIL, ctx->prof ? bytes_S(L, P, start, j) : 0.0);
             launch_outer_S(L, j, s);
-            prof_end(ctx, r, s);
+            L.ev = {};
             if (j < L.kmax) {
-                r = prof_begin(ctx, NKS_K_RECUR, ctx->prof ? bytes_R(L, P, start, j) : 0.0, s);
+                L.ev = prof_take(ctx, NKS_K_RECUR, ctx->prof ? bytes_R(L, P, start, j) : 0.0);
                 launch_outer_R(L, j, s);
-                prof_end(ctx, r, s);
+                L.ev = {};
                 if (learned && j == LEARN_K0) launch_predict(L.jobs, L.njobs, j, s);
                 // plain checkpoints every CKPT_DK; a learned k target is a multiple of LEARN_DK
                 if (kpol && (j % CKPT_DK == 0 || (klearned && j > LEARN_K0 && j % LEARN_DK == 0)))
@@ -482,19 +489,11 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
         }
         if (pipe) {
             launch_finalize(L.jobs, L.njobs, s);
-            const long long c = ctx->prof_count[NKS_K_NESTED];
-            ctx->prof_count[NKS_K_NESTED] = 0;
-            int r = prof_begin(ctx, NKS_K_NESTED, 0.0, s);
-            ctx->prof_count[NKS_K_NESTED] = c + 1;
-            launch_nested(L.jobs, L.njobs, s);
-            prof_end(ctx, r, s);
+            launch_nested(L.jobs, L.njobs, s, prof_take_always(ctx, NKS_K_NESTED, 0.0));
             enqueue_second_pass(L, s);
-            const long long c2 = ctx->prof_count[NKS_K_LIFT];
-            ctx->prof_count[NKS_K_LIFT] = 0;
-            r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, start) : 0.0, s);
-            ctx->prof_count[NKS_K_LIFT] = c2 + 1;
+            L.ev = prof_take_always(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, start) : 0.0);
             launch_lift(L, s);
-            prof_end(ctx, r, s);
+            L.ev = {};
         }
     }
     frc = join_groups(ctx, ng, s0);
@@ -511,14 +510,7 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
         HIP_TRY(ctx, hipGetLastError());
         return NKS_OK;
     }
-    {
-        const long long c = ctx->prof_count[NKS_K_NESTED];
-        ctx->prof_count[NKS_K_NESTED] = 0;   // the nested launch is always timed when profiling
-        int r = prof_begin(ctx, NKS_K_NESTED, 0.0, s);
-        ctx->prof_count[NKS_K_NESTED] = c + 1;
-        launch_nested(table, (int)descs.size(), s);
-        prof_end(ctx, r, s);
-    }
+    launch_nested(table, (int)descs.size(), s, prof_take_always(ctx, NKS_K_NESTED, 0.0));
     HIP_TRY(ctx, hipGetLastError());
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[2], s));
     frc = fork_groups(ctx, ng, s0);
@@ -527,12 +519,8 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
         hipStream_t sl = group_stream(ctx, gi, ng, s0);
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         enqueue_second_pass(L, sl);
-        const long long c = ctx->prof_count[NKS_K_LIFT];
-        ctx->prof_count[NKS_K_LIFT] = 0;
-        int r = prof_begin(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0, sl);
-        ctx->prof_count[NKS_K_LIFT] = c + 1;
+        L.ev = prof_take_always(ctx, NKS_K_LIFT, ctx->prof ? bytes_lift(L, P, P.groups[gi].first) : 0.0);
         launch_lift(L, sl);
-        prof_end(ctx, r, sl);
     }
     frc = join_groups(ctx, ng, s0);
     if (frc) return frc;

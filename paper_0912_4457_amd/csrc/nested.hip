@@ -16,6 +16,8 @@
 // With ell >= k_used the RHi runs on H_k itself (non-nested method).
 #include "nks_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace nks {
 
 namespace {
@@ -1524,8 +1526,11 @@ void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(njobs), dim3(NT), 0, s, jobs);
 }
 
-void launch_nested(JobDesc* jobs, int njobs, hipStream_t s) {
-    hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_FINAL, 0);
+void launch_nested(JobDesc* jobs, int njobs, hipStream_t s, LaunchEvents ev) {
+    if (ev.a)
+        hipExtLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, ev.a, ev.b, 0, jobs, (int)NEST_FINAL, 0);
+    else
+        hipLaunchKernelGGL(nested_kernel, dim3(njobs), dim3(NT), 0, s, jobs, (int)NEST_FINAL, 0);
 }
 
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s) {

@@ -245,6 +245,13 @@ struct Tuning {
     int pipeline = 0;     // with concurrent groups: each group's nested step and lift follow its own outer loop
 };
 
+// Start/stop events of a timed launch (nks_profile_enable), stamped by the
+// kernel's own dispatch packet (hipExtLaunchKernelGGL), so that they bracket
+// its execution and not the gaps between launches.  Null: an ordinary launch.
+struct LaunchEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
 // outer.hip
 struct OuterLaunch {
     Geom g;
@@ -260,6 +267,7 @@ struct OuterLaunch {
     int deflate;           // some job of the group is deflated
     int ring;              // some job of the group runs in double-pass mode
     int pass2;             // 1: the second (regenerating) pass of those jobs
+    LaunchEvents ev;       // timing of the next S, R or lift launch
 };
 constexpr int OUTER_NT = 128;
 
@@ -309,7 +317,7 @@ void launch_lift(const OuterLaunch& L, hipStream_t s);
 // nested.hip
 constexpr int NEST_NT = 256;
 void launch_finalize(JobDesc* jobs, int njobs, hipStream_t s);
-void launch_nested(JobDesc* jobs, int njobs, hipStream_t s);
+void launch_nested(JobDesc* jobs, int njobs, hipStream_t s, LaunchEvents ev = {});
 void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // after R_j
 void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s);      // after R_{k0}
 void launch_label(JobDesc* jobs, int njobs, hipStream_t s);               // after the outer loop

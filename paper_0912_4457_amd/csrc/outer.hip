@@ -24,6 +24,8 @@
 // summation order of the lift).
 #include "wilson.h"
 
+#include <hip/hip_ext.h>
+
 namespace nks {
 
 namespace {
@@ -468,6 +470,13 @@ void launch_pack(const OuterLaunch& L, hipStream_t s) {
         hipLaunchKernelGGL(pack_kernel<float>, grid, dim3(NT), 0, s, L.jobs, L.g.V, L.nblocks, L.pass2);
 }
 
+// A launch of the outer passes: timed through the dispatch packet when L.ev is set.
+template <typename F, typename... Args>
+static void dispatch(const OuterLaunch& L, F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    if (L.ev.a) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, L.ev.a, L.ev.b, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 static dim3 outer_grid(const OuterLaunch& L, int z) {
     if (L.tune.xcd_map) return dim3(8 * xcd_slots(L.nblocks, L.njobs, L.tune.xcd_map), 1, z);
     return dim3(L.nblocks, L.njobs, z);
@@ -478,14 +487,14 @@ static void outer_S_w(const OuterLaunch& L, int j, hipStream_t s) {
     auto links = static_cast<const cx_t<R>*>(L.links);
     const int xm = L.tune.xcd_map;
     if (!L.two_sided) {
-        hipLaunchKernelGGL((herm_S<R, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa, j,
-                           L.nblocks, L.njobs, xm, L.pass2);
+        dispatch(L, herm_S<R, MINW>, outer_grid(L, 1), dim3(NT), s, L.jobs, L.g, links, L.kappa, j, L.nblocks,
+                 L.njobs, xm, L.pass2);
     } else if (L.tune.split_dual) {
-        hipLaunchKernelGGL((bi_S<R, true, MINW>), outer_grid(L, 2), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
-                           L.mu, j, L.nblocks, L.njobs, xm, L.pass2);
+        dispatch(L, bi_S<R, true, MINW>, outer_grid(L, 2), dim3(NT), s, L.jobs, L.g, links, L.kappa, L.mu, j,
+                 L.nblocks, L.njobs, xm, L.pass2);
     } else {
-        hipLaunchKernelGGL((bi_S<R, false, MINW>), outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g, links, L.kappa,
-                           L.mu, j, L.nblocks, L.njobs, xm, L.pass2);
+        dispatch(L, bi_S<R, false, MINW>, outer_grid(L, 1), dim3(NT), s, L.jobs, L.g, links, L.kappa, L.mu, j,
+                 L.nblocks, L.njobs, xm, L.pass2);
     }
 }
 
@@ -502,11 +511,9 @@ template <typename R>
 static void outer_R(const OuterLaunch& L, int j, hipStream_t s) {
     const int xm = L.tune.xcd_map;
     if (!L.two_sided)
-        hipLaunchKernelGGL(herm_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm,
-                           L.pass2);
+        dispatch(L, herm_R<R>, outer_grid(L, 1), dim3(NT), s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm, L.pass2);
     else
-        hipLaunchKernelGGL(bi_R<R>, outer_grid(L, 1), dim3(NT), 0, s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm,
-                           L.pass2);
+        dispatch(L, bi_R<R>, outer_grid(L, 1), dim3(NT), s, L.jobs, L.g.V, j, L.nblocks, L.njobs, xm, L.pass2);
 }
 
 void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s) {
@@ -523,9 +530,9 @@ void launch_lift(const OuterLaunch& L, hipStream_t s) {
     const int n = 12 * L.g.V;
     dim3 grid((n + LIFT_NT - 1) / LIFT_NT, L.njobs);
     if (L.precision == NKS_FP64)
-        hipLaunchKernelGGL(lift_kernel<double>, grid, dim3(LIFT_NT), 0, s, L.jobs, L.g.V);
+        dispatch(L, lift_kernel<double>, grid, dim3(LIFT_NT), s, L.jobs, L.g.V);
     else
-        hipLaunchKernelGGL(lift_kernel<float>, grid, dim3(LIFT_NT), 0, s, L.jobs, L.g.V);
+        dispatch(L, lift_kernel<float>, grid, dim3(LIFT_NT), s, L.jobs, L.g.V);
 }
 
 }  // namespace nks

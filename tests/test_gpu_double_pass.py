@@ -141,3 +141,45 @@ def test_double_pass_16x4_pure_gauge_closed_form(mu, k, ell, tol):
     x, st = nks.sign_apply(lat, b.ravel(), k=k, ell=ell, double_pass=True)
     assert st["status"] == 0
     assert rel(to_np(x), ref) <= tol
+
+
+def test_double_pass_and_levels_in_graph_replays_match_eager():
+    # the second pass and the deeper levels inside captured graphs: every
+    # replay (with eager work and synchronisation between) gives the eager bits
+    import math
+    import torch
+    import paper_0912_4457_amd as nks
+    c = nks.Context(0)
+    u = I.su3_links(DIMS, 0.5, 4401)
+    lats = [nks.Lattice(c, DIMS, u, mu=0.0), nks.Lattice(c, DIMS, u, mu=0.3)]
+    jobs = []
+    for lat in lats:
+        for s, extra in enumerate((dict(double_pass=True), dict(ell_deep=[12, 4]),
+                                   dict(double_pass=True, ell_deep=[16, 6], overlap=True))):
+            b = torch.from_numpy(I.gaussian_source(DIMS, 60 + s).ravel()).cuda()
+            jobs.append(dict(lat=lat, b=b, x=torch.empty_like(b), k=140, ell=40, **extra))
+
+    def run(graph):
+        c.tune_set("graph", int(graph))
+        xs, _ = nks.sign_apply_batch(jobs, stats=False)
+        torch.cuda.synchronize()
+        return [to_np(x).copy() for x in xs]
+
+    ref = run(False)
+    for rep in range(3):
+        got = run(True)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+        y = nks.apply_op(lats[1], jobs[0]["b"])
+        torch.cuda.synchronize()
+        assert math.isfinite(float(torch.linalg.vector_norm(y)))
+    assert c.tune_get("graph_replays") >= 2
+    c.tune_set("graph", 1)
+
+
+def test_double_pass_with_learned_policy_equals_single_pass():
+    import paper_0912_4457_amd as nks
+    nks.load_policy(ctx())
+    lat = lattice(DIMS, 0.5, 4401, 0.0)
+    _pairs_of_runs([dict(lat=lat, b=I.gaussian_source(DIMS, 31).ravel(), k=1000, ell=256, tol=1e-8,
+                         k_policy=nks.POLICY_LEARNED, ell_policy=nks.POLICY_LEARNED)])
