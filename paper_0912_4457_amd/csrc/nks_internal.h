@@ -276,21 +276,29 @@ constexpr int OUTER_NT = 128;
 // which part of the (site block, job) rectangle each XCD's L2 serves:
 //   1: a contiguous eighth of the site blocks, all jobs (jobs innermost);
 //   2: a contiguous eighth of the (job, site block) pairs, job-major;
-//   3: half of the site blocks (a contiguous half in t) for a quarter of the
-//      jobs: each XCD fetches a t-halo of two slices per half lattice
-//      instead of per eighth, and the links of its half for its jobs.
+//   3: the XCDs split into JP parts of the jobs times 8 / JP contiguous
+//      parts of the site blocks (in t), JP = 4 for at least 8 jobs or a
+//      multiple of 4, 2 for 2..7 jobs, 1 for one job: at 12 jobs each XCD
+//      fetches a t-halo of two slices per half lattice instead of per eighth.
 // xcd_slots is the number of workgroups per XCD (grid = 8 * slots);
 // map_block returns false for padding workgroups.
+__host__ __device__ inline int xcd_job_parts(int njobs) {
+    return (njobs >= 8 || njobs % 4 == 0) ? 4 : (njobs >= 2 ? 2 : 1);
+}
 __host__ __device__ inline int xcd_slots(int nblocks, int njobs, int xcd_map) {
-    if (xcd_map == 3) return ((nblocks + 1) / 2) * ((njobs + 3) / 4);
+    if (xcd_map == 3) {
+        const int jp = xcd_job_parts(njobs), tp = 8 / jp;
+        return ((nblocks + tp - 1) / tp) * ((njobs + jp - 1) / jp);
+    }
     return (nblocks * njobs + 7) / 8;
 }
 __host__ __device__ inline bool map_block(int b, int nblocks, int njobs, int xcd_map, int& sb, int& job) {
     const int x = b & 7, i = b >> 3;
     if (xcd_map == 3) {
-        const int tp = x & 1, jp = x >> 1;
-        const int sb_lo = tp * nblocks / 2, sb_hi = (tp + 1) * nblocks / 2;
-        const int j_lo = jp * njobs / 4, j_hi = (jp + 1) * njobs / 4;
+        const int JP = xcd_job_parts(njobs), TP = 8 / JP;
+        const int tp = x % TP, jp = x / TP;
+        const int sb_lo = tp * nblocks / TP, sb_hi = (tp + 1) * nblocks / TP;
+        const int j_lo = jp * njobs / JP, j_hi = (jp + 1) * njobs / JP;
         const int m = j_hi - j_lo;
         if (m <= 0 || i >= (sb_hi - sb_lo) * m) return false;
         sb = sb_lo + i / m;
