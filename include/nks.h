@@ -193,6 +193,25 @@ void nks_lattice_destroy(nks_lattice* lat);
 int nks_lattice_set_deflation(nks_lattice* lat, int m, const void* r_dev, const void* l_dev,
                               const double* lambda_host);
 
+/* Deflation eigenpairs computed on the GPU for the Hermitian A (mu = 0;
+ * NKS_E_UNSUPPORTED otherwise): the m (1..64) eigenpairs of A with the
+ * smallest |lambda| (App. C step 1), by Chebyshev-filtered subspace
+ * iteration on A^2 (a block of m + max(8, m) vectors, filter degree 40,
+ * the interval bound (1 + 8 sqrt(2) kappa)^2 >= ||A||^2, Rayleigh-Ritz on
+ * A^2, then on A within the m converged vectors), until every
+ * |A r_i - lambda_i r_i| <= tol (r_i unit vectors) or max_iter
+ * iterations.  On success the pairs are installed on the lattice as by
+ * nks_lattice_set_deflation; on NKS_E_NOCONV the lattice keeps no deflation.
+ * lambda_host, resid_host (m doubles each, ascending |lambda|) and iters
+ * may be NULL.  The p x p Rayleigh-Ritz and Cholesky steps run on the host.
+ * Uses the null stream and waits. */
+int nks_lattice_eigensolve(nks_lattice* lat, int m, int max_iter, double tol, double* lambda_host,
+                           double* resid_host, int* iters);
+/* The lattice's deflation eigenvectors (as set or computed above): *m_out =
+ * their number; r_dev, l_dev (device, m complex128 vectors each in the
+ * caller's layout, either may be NULL) receive copies.  Waits. */
+int nks_lattice_get_deflation(nks_lattice* lat, int* m_out, void* r_dev, void* l_dev);
+
 /* out = A in (dagger = 0) or A^dagger in (dagger = 1), A = gamma5 D_w(mu);
  * A(mu)^dagger = gamma5 D_w(-mu).  precision NKS_MIXED runs the float32
  * stencil (inputs and outputs stay complex128).  in and out must not alias. */

@@ -92,6 +92,8 @@ SIGNATURES = {
     "nks_lattice_set_params": (_I, [_VP, _D, _D]),
     "nks_lattice_destroy": (None, [_VP]),
     "nks_lattice_set_deflation": (_I, [_VP, _I, _VP, _VP, _PD]),
+    "nks_lattice_eigensolve": (_I, [_VP, _I, _I, _D, _PD, _PD, ctypes.POINTER(_I)]),
+    "nks_lattice_get_deflation": (_I, [_VP, ctypes.POINTER(_I), _VP, _VP]),
     "nks_apply_op": (_I, [_VP, _VP, _VP, _I, _I, _VP]),
     "nks_workspace_size": (_I, [_VP, _I, ctypes.POINTER(Job), ctypes.POINTER(_SZ)]),
     "nks_sign_apply": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
@@ -260,6 +262,32 @@ class Lattice:
     def set_params(self, m0: float, mu: float):
         self.ctx.check(lib().nks_lattice_set_params(self.h, float(m0), float(mu)))
         self.m0, self.mu = float(m0), float(mu)
+
+    def compute_deflation(self, m: int, max_iter: int = 300, tol: float = 1e-10):
+        """The m eigenpairs of the Hermitian A (mu = 0) with the smallest |lambda|,
+        computed on the GPU and installed for deflate=True jobs (see
+        nks_lattice_eigensolve).  Returns (eigenvalues, residuals, iterations)."""
+        lam = np.zeros(m)
+        res = np.zeros(m)
+        it = ctypes.c_int()
+        self.ctx.check(lib().nks_lattice_eigensolve(self.h, int(m), int(max_iter), float(tol),
+                                                    lam.ctypes.data_as(_PD), res.ctypes.data_as(_PD),
+                                                    ctypes.byref(it)))
+        self._defl = None
+        return lam, res, it.value
+
+    def deflation_vectors(self):
+        """(r, l): the lattice's deflation eigenvectors as (m, 12*V) complex128
+        device tensors in the caller's layout (copies); m = 0 gives empty ones."""
+        torch = _torch()
+        m = ctypes.c_int()
+        self.ctx.check(lib().nks_lattice_get_deflation(self.h, ctypes.byref(m), None, None))
+        r = torch.empty((m.value, self.n), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        l = torch.empty_like(r)
+        if m.value:
+            self.ctx.check(lib().nks_lattice_get_deflation(self.h, ctypes.byref(m), ctypes.c_void_p(r.data_ptr()),
+                                                           ctypes.c_void_p(l.data_ptr())))
+        return r, l
 
     def set_deflation(self, r, lam, l=None):
         """Eigenpairs for deflate=True jobs: r (and l, default r) of shape

@@ -12,6 +12,11 @@
 
 #include "nks_internal.h"
 
+namespace {
+constexpr int EIG_DEGREE = 40;                    // Chebyshev filter degree of the eigensolver
+constexpr unsigned long long EIG_SEED = 20091224;  // its start block
+}  // namespace
+
 using namespace nks;
 
 struct ProfRecord {
@@ -90,6 +95,16 @@ __global__ void vecs_to_soa(const double2* __restrict__ in, double2* __restrict_
     const long long i = e / n, r = e - i * n;
     const int c = (int)(r / V), s = (int)(r - (long long)c * V);
     out[e] = in[i * n + 12LL * s + c];
+}
+
+// [i][comp][site] -> caller layout [i][12*site + comp]
+__global__ void vecs_from_soa(const double2* __restrict__ in, double2* __restrict__ out, int V, int m) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;   // e = (i * 12 + comp) * V + site
+    const long long n = 12LL * V;
+    if (e >= n * m) return;
+    const long long i = e / n, r = e - i * n;
+    const int c = (int)(r / V), s = (int)(r - (long long)c * V);
+    out[i * n + 12LL * s + c] = in[e];
 }
 
 __global__ void links_to_soa(const double2* __restrict__ in, double2* __restrict__ o64, float2* __restrict__ o32,
@@ -782,6 +797,69 @@ int nks_lattice_set_deflation(nks_lattice* lat, int m, const void* r_dev, const 
         HIP_TRY(ctx, hipDeviceSynchronize());
     }
     lat->defl_m = m;
+    return NKS_OK;
+}
+
+int nks_lattice_eigensolve(nks_lattice* lat, int m, int max_iter, double tol, double* lambda_host,
+                           double* resid_host, int* iters) {
+    if (!lat) return NKS_E_INVALID;
+    nks_ctx* ctx = lat->ctx;
+    if (m < 1 || m > DEFL_MAX) return fail(ctx, NKS_E_INVALID, "the eigensolver takes 1 <= m <= 64 eigenpairs");
+    if (max_iter < 1 || !(tol > 0.0)) return fail(ctx, NKS_E_INVALID, "max_iter must be >= 1 and tol > 0");
+    if (lat->mu != 0.0) return fail(ctx, NKS_E_UNSUPPORTED, "the eigensolver handles the Hermitian case (mu = 0) only");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());     // no call in flight may read the old eigenpairs
+    const size_t n = (size_t)12 * lat->g.V;
+    if (m > lat->defl_cap) {
+        (void)hipFree(lat->defl_r);
+        (void)hipFree(lat->defl_l);
+        (void)hipFree(lat->defl_sgn);
+        lat->defl_r = lat->defl_l = nullptr;
+        lat->defl_sgn = nullptr;
+        lat->defl_cap = lat->defl_m = 0;
+        HIP_TRY(ctx, hipMalloc(&lat->defl_r, sizeof(double2) * n * m));
+        HIP_TRY(ctx, hipMalloc(&lat->defl_l, sizeof(double2) * n * m));
+        HIP_TRY(ctx, hipMalloc(&lat->defl_sgn, sizeof(double) * m));
+        lat->defl_cap = m;
+    }
+    lat->defl_m = 0;
+    const int p = m + std::max(8, m);
+    std::vector<double> lam(m), res(m);
+    int it = 0;
+    std::string err;
+    const int rc = eig_chfsi(lat->g, lat->links64, lat->kappa, m, p, EIG_DEGREE, max_iter, tol, EIG_SEED,
+                             lat->defl_r, lam.data(), res.data(), &it, err);
+    if (iters) *iters = it;
+    for (int i = 0; i < m; ++i) {
+        if (lambda_host) lambda_host[i] = lam[i];
+        if (resid_host) resid_host[i] = res[i];
+    }
+    if (rc != NKS_OK) return fail(ctx, rc, err);
+    std::vector<double> sg(m);
+    for (int i = 0; i < m; ++i) {
+        if (!(lam[i] != 0.0)) return fail(ctx, NKS_E_NOCONV, "eigensolver: a zero eigenvalue has no sign");
+        sg[i] = lam[i] > 0.0 ? 1.0 : -1.0;
+    }
+    HIP_TRY(ctx, hipMemcpy(lat->defl_l, lat->defl_r, sizeof(double2) * n * m, hipMemcpyDeviceToDevice));
+    HIP_TRY(ctx, hipMemcpy(lat->defl_sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    lat->defl_m = m;
+    return NKS_OK;
+}
+
+int nks_lattice_get_deflation(nks_lattice* lat, int* m_out, void* r_dev, void* l_dev) {
+    if (!lat || !m_out) return NKS_E_INVALID;
+    nks_ctx* ctx = lat->ctx;
+    *m_out = lat->defl_m;
+    const int m = lat->defl_m;
+    if (m == 0 || (!r_dev && !l_dev)) return NKS_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const long long tot = 12LL * lat->g.V * m;
+    const int nb = (int)((tot + 255) / 256);
+    if (r_dev) hipLaunchKernelGGL(vecs_from_soa, dim3(nb), dim3(256), 0, nullptr, lat->defl_r, static_cast<double2*>(r_dev), lat->g.V, m);
+    if (l_dev) hipLaunchKernelGGL(vecs_from_soa, dim3(nb), dim3(256), 0, nullptr, lat->defl_l, static_cast<double2*>(l_dev), lat->g.V, m);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipDeviceSynchronize());
     return NKS_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/nks.h"
 
 namespace nks {
@@ -330,6 +332,12 @@ void launch_checkpoint(JobDesc* jobs, int njobs, int j, hipStream_t s);   // aft
 void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s);      // after R_{k0}
 void launch_label(JobDesc* jobs, int njobs, hipStream_t s);               // after the outer loop
 size_t nest_words(int k, int ell, int levels, const int* ell_deep);
+
+// eig.hip: m eigenpairs of the Hermitian A with the smallest |lambda| by a
+// block of p >= m vectors; the eigenvectors go to vecs_out (SoA [i][comp][site]).
+int eig_chfsi(const Geom& g, const double2* links, double kappa, int m, int p, int degree, int max_iter, double tol,
+              unsigned long long seed, double2* vecs_out, double* lambda_out, double* resid_out, int* iters_out,
+              std::string& err);
 
 // mlp.hip
 int mlp_nparams();
