@@ -96,3 +96,18 @@ def test_eigensolve_errors():
     assert e.value.code == 6
     r, _ = lat.deflation_vectors()
     assert r.shape[0] == 0
+
+
+def test_sign_of_computed_eigenvectors():
+    # sgn(A) r = sgn(lambda) r for the eigenpairs the eigensolver returns (Eq. fAdef)
+    import paper_0912_4457_amd as nks
+    lat = lattice(DIMS, 0.5, 4401, 0.0)
+    try:
+        lam, res, it = lat.compute_deflation(4, tol=1e-11)
+        r, _ = lat.deflation_vectors()
+    finally:
+        lat.set_deflation(None, [])
+    for i in range(4):
+        x, st = nks.sign_apply(lat, r[i].clone(), k=300, ell=80)
+        assert st["status"] == 0
+        assert rel(to_np(x), np.sign(lam[i]) * to_np(r[i])) <= 1e-9
