@@ -70,12 +70,16 @@ def recorded_traffic(tuning=None):
             vals[k_.strip()] = v_.strip()
     if vals.get("source_sha") != source_hash():
         return None
-    if tuning is not None and vals.get("tuning") != tuning_str(tuning):
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    # one counter set per launch tuning: "tuning" / "hbm_bytes_per_launch", then ".2", ".3", ...
+    for suffix in ("", ".2", ".3", ".4"):
+        if f"tuning{suffix}" not in vals and suffix:
+            break
+        if tuning is None or vals.get(f"tuning{suffix}") == tuning_str(tuning):
+            try:
+                return float(vals[f"hbm_bytes_per_launch{suffix}"])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def golden_samples():
@@ -617,7 +621,8 @@ def main():
         "p_used": sorted(set(round(s["p_used"], 4) for s in sts)),
         "other_path": {"precision": other,
                        "value": other_run["napps"] * other_run["steps"] / other_run["seconds"],
-                       "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None)},
+                       "max_rel_err_vs_oracle": (max(other_run["errs"]) if other_run["errs"] else None),
+                       "rel_err_vs_oracle_per_source": other_run["errs"]},
         "batches_in_flight": {"count": INFLIGHT, "value": value,
                               "one_batch_at_a_time_value": (main_run["napps"] * a.steps / main_run["one_stream_seconds"]
                                                             if main_run["one_stream_seconds"] else None)},
