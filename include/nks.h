@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define NKS_ABI_VERSION 2
+#define NKS_ABI_VERSION 3
 
 /* Largest number of nested levels (Sec. 4.5); see nks_opts.levels. */
 #define NKS_MAX_LEVELS 6
@@ -193,17 +193,21 @@ void nks_lattice_destroy(nks_lattice* lat);
 int nks_lattice_set_deflation(nks_lattice* lat, int m, const void* r_dev, const void* l_dev,
                               const double* lambda_host);
 
-/* Deflation eigenpairs computed on the GPU for the Hermitian A (mu = 0;
- * NKS_E_UNSUPPORTED otherwise): the m (1..64) eigenpairs of A with the
- * smallest |lambda| (App. C step 1), by Chebyshev-filtered subspace
- * iteration on A^2 (a block of m + max(8, m) vectors, filter degree 40,
- * the interval bound (1 + 8 sqrt(2) kappa)^2 >= ||A||^2, Rayleigh-Ritz on
- * A^2, then on A within the m converged vectors), until every
- * |A r_i - lambda_i r_i| <= tol (r_i unit vectors) or max_iter
- * iterations.  On success the pairs are installed on the lattice as by
- * nks_lattice_set_deflation; on NKS_E_NOCONV the lattice keeps no deflation.
- * lambda_host, resid_host (m doubles each, ascending |lambda|) and iters
- * may be NULL.  The p x p Rayleigh-Ritz and Cholesky steps run on the host.
+/* Deflation eigenpairs computed on the GPU: the m (1..64) eigenpairs of A
+ * with the smallest |lambda| (App. C step 1), by Chebyshev-filtered subspace
+ * iteration on A^2 (a block of m + max(8, m) vectors, filter degree 40, the
+ * interval bound ||A||^2 <= (1 + kappa (6 sqrt(2) + 2 sqrt(2 cosh 2mu)))^2,
+ * Rayleigh-Ritz on A^2 ordered by |theta^2|, then on A within the first m
+ * vectors), until every |A r_i - lambda_i r_i| <= tol (r_i unit vectors) or
+ * max_iter iterations.  mu = 0: l_i = r_i.  mu != 0: the left eigenvectors
+ * come from a second run on A^dagger = A(-mu), paired by eigenvalue and
+ * scaled to l_i^dagger r_i = 1; the residuals are the larger of the two
+ * runs' and iters counts both; NKS_E_NOCONV also if the two sets do not
+ * pair up (a tie in |lambda| at the m-th eigenvalue).  On success the pairs
+ * are installed on the lattice as by nks_lattice_set_deflation; on an error
+ * the lattice keeps no deflation.  lambda_host (2m doubles, interleaved
+ * complex, ascending |lambda|), resid_host (m doubles) and iters may be
+ * NULL.  The p x p Cholesky, Jacobi and Hessenberg-QR steps run on the host.
  * Uses the null stream and waits. */
 int nks_lattice_eigensolve(nks_lattice* lat, int m, int max_iter, double tol, double* lambda_host,
                            double* resid_host, int* iters);

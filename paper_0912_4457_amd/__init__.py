@@ -264,17 +264,18 @@ class Lattice:
         self.m0, self.mu = float(m0), float(mu)
 
     def compute_deflation(self, m: int, max_iter: int = 300, tol: float = 1e-10):
-        """The m eigenpairs of the Hermitian A (mu = 0) with the smallest |lambda|,
-        computed on the GPU and installed for deflate=True jobs (see
-        nks_lattice_eigensolve).  Returns (eigenvalues, residuals, iterations)."""
-        lam = np.zeros(m)
+        """The m eigenpairs of A with the smallest |lambda|, computed on the GPU
+        (left eigenvectors too when mu != 0) and installed for deflate=True jobs
+        (see nks_lattice_eigensolve).  Returns (complex eigenvalues ascending in
+        |lambda|, residuals, iterations)."""
+        lam = np.zeros(2 * m)
         res = np.zeros(m)
         it = ctypes.c_int()
         self.ctx.check(lib().nks_lattice_eigensolve(self.h, int(m), int(max_iter), float(tol),
                                                     lam.ctypes.data_as(_PD), res.ctypes.data_as(_PD),
                                                     ctypes.byref(it)))
         self._defl = None
-        return lam, res, it.value
+        return lam[0::2] + 1j * lam[1::2], res, it.value
 
     def deflation_vectors(self):
         """(r, l): the lattice's deflation eigenvectors as (m, 12*V) complex128

@@ -806,7 +806,6 @@ int nks_lattice_eigensolve(nks_lattice* lat, int m, int max_iter, double tol, do
     nks_ctx* ctx = lat->ctx;
     if (m < 1 || m > DEFL_MAX) return fail(ctx, NKS_E_INVALID, "the eigensolver takes 1 <= m <= 64 eigenpairs");
     if (max_iter < 1 || !(tol > 0.0)) return fail(ctx, NKS_E_INVALID, "max_iter must be >= 1 and tol > 0");
-    if (lat->mu != 0.0) return fail(ctx, NKS_E_UNSUPPORTED, "the eigensolver handles the Hermitian case (mu = 0) only");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipDeviceSynchronize());     // no call in flight may read the old eigenpairs
     const size_t n = (size_t)12 * lat->g.V;
@@ -824,23 +823,26 @@ int nks_lattice_eigensolve(nks_lattice* lat, int m, int max_iter, double tol, do
     }
     lat->defl_m = 0;
     const int p = m + std::max(8, m);
-    std::vector<double> lam(m), res(m);
+    std::vector<double> lam(2 * m), res(m);
     int it = 0;
     std::string err;
-    const int rc = eig_chfsi(lat->g, lat->links64, lat->kappa, m, p, EIG_DEGREE, max_iter, tol, EIG_SEED,
-                             lat->defl_r, lam.data(), res.data(), &it, err);
+    const int rc = eig_chfsi(lat->g, lat->links64, lat->kappa, lat->mu, m, p, EIG_DEGREE, max_iter, tol, EIG_SEED,
+                             lat->defl_r, lat->defl_l, lam.data(), res.data(), &it, err);
     if (iters) *iters = it;
     for (int i = 0; i < m; ++i) {
-        if (lambda_host) lambda_host[i] = lam[i];
+        if (lambda_host) {
+            lambda_host[2 * i] = lam[2 * i];
+            lambda_host[2 * i + 1] = lam[2 * i + 1];
+        }
         if (resid_host) resid_host[i] = res[i];
     }
     if (rc != NKS_OK) return fail(ctx, rc, err);
     std::vector<double> sg(m);
-    for (int i = 0; i < m; ++i) {
-        if (!(lam[i] != 0.0)) return fail(ctx, NKS_E_NOCONV, "eigensolver: a zero eigenvalue has no sign");
-        sg[i] = lam[i] > 0.0 ? 1.0 : -1.0;
+    for (int i = 0; i < m; ++i) {   // sgn(lambda) = sgn(Re lambda)
+        const double re = lam[2 * i];
+        if (!(re != 0.0)) return fail(ctx, NKS_E_NOCONV, "eigensolver: an eigenvalue with Re(lambda) = 0 has no sign");
+        sg[i] = re > 0.0 ? 1.0 : -1.0;
     }
-    HIP_TRY(ctx, hipMemcpy(lat->defl_l, lat->defl_r, sizeof(double2) * n * m, hipMemcpyDeviceToDevice));
     HIP_TRY(ctx, hipMemcpy(lat->defl_sgn, sg.data(), sizeof(double) * m, hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipDeviceSynchronize());
     lat->defl_m = m;

@@ -1,22 +1,28 @@
-// Deflation eigenpairs of the Hermitian A = gamma5 D_w(0) (App. C step 1
-// needs the eigenpairs of A with the smallest |lambda|; the paper takes them
-// from a separate eigensolver).  Chebyshev-filtered subspace iteration on a
-// block of p vectors:
+// Deflation eigenpairs of A = gamma5 D_w(mu) (App. C step 1 needs the
+// eigenpairs of A with the smallest |lambda|; the paper takes them from a
+// separate eigensolver).  Chebyshev-filtered subspace iteration on a block
+// of p vectors:
 //
 //   filter    X <- T_d(A^2) X, a Chebyshev polynomial of degree d in A^2 that
-//             damps [a, b] (a = the largest squared Ritz value of the block,
-//             b = (1 + 8 sqrt(2) kappa)^2 >= ||A||^2) and grows below a;
-//   orthonormalise  X <- X R^{-1} twice, R from the Cholesky factor of X^H X;
-//   Rayleigh-Ritz on A^2   (AX)^H (AX) = W diag(theta^2) W^H, X <- X W: the
-//             squared Ritz values are extremal, so none of them is spurious
-//             (Rayleigh-Ritz on the indefinite A itself makes spurious
-//             values near 0 from mixtures of +lambda and -lambda modes);
-//   eigenpairs  Rayleigh-Ritz on A within the m vectors of the smallest
-//             squared Ritz values, and the residuals |A x - theta x|.
+//             damps [a, b] (a = the largest squared Ritz value of the block in
+//             modulus, b >= ||A||^2) and grows below a;
+//   orthonormalise  X <- X L^{-H} twice, L the Cholesky factor of X^H X;
+//   Rayleigh-Ritz on A^2   order the block by |theta^2|.  Hermitian A:
+//             (AX)^H (AX) = W diag(theta^2) W^H, X <- X W.  Otherwise the Ritz
+//             vectors of X^H A^2 X in that order, orthonormalised again (which
+//             keeps the span of every leading group).  Squared Ritz values sit
+//             at the low end of the spectrum of A^2, where Rayleigh-Ritz on the
+//             indefinite A itself makes spurious values near 0 (mixtures of
+//             +lambda and -lambda modes);
+//   eigenpairs  Rayleigh-Ritz on A within the first m vectors, and the
+//             residuals |A x - theta x| of the unit Ritz vectors.
 //
-// The stencil, the filter recurrence, the Gram matrices X^H Y and the basis
-// rotations X Z run on the GPU; the p x p Cholesky and Jacobi steps (p <= 128)
-// run on the host in double precision.  Vectors are SoA blocks
+// For mu != 0 the left eigenvectors are the right eigenvectors of
+// A^dagger = A(-mu) (eigenvalues conj(lambda)): a second run on A(-mu), the
+// two sets paired by eigenvalue and scaled to l_i^dagger r_i = 1.  The
+// stencil, the filter recurrence, the Gram matrices X^H Y and the basis
+// rotations X Z run on the GPU; the p x p steps (dense_host.h, p <= 128) run
+// on the host in double precision.  Vectors are SoA blocks
 // [vector][comp = 3 spin + colour][site] of complex128.
 #include <algorithm>
 #include <cmath>
@@ -25,6 +31,7 @@
 #include <string>
 #include <vector>
 
+#include "dense_host.h"
 #include "wilson.h"
 
 namespace nks {
@@ -33,9 +40,10 @@ namespace {
 
 constexpr int ENT = 128;   // threads per block of the site-parallel kernels
 constexpr int GNT = 256;   // threads per block of the reductions
+constexpr int ROT = 8;     // outputs per thread of eig_rotate
 
-// out_v = alpha (A in_v) + beta y_v + gamma z_v for v = blockIdx.y (y, z may be null)
-__global__ __launch_bounds__(ENT) void eig_apply(Geom g, const double2* __restrict__ links, double kappa,
+// out_v = alpha (A(mu) in_v) + beta y_v + gamma z_v for v = blockIdx.y (y, z may be null)
+__global__ __launch_bounds__(ENT) void eig_apply(Geom g, const double2* __restrict__ links, double kappa, double mu,
                                                  const double2* __restrict__ in, double2* __restrict__ out,
                                                  double alpha, const double2* __restrict__ y, double beta,
                                                  const double2* __restrict__ z, double gamma) {
@@ -44,7 +52,7 @@ __global__ __launch_bounds__(ENT) void eig_apply(Geom g, const double2* __restri
     const size_t n = (size_t)12 * g.V;
     const size_t off = (size_t)blockIdx.y * n;
     double cf[1][4], cb[1][4];
-    hop_coefs<double>(kappa, 0.0, cf[0], cb[0]);
+    hop_coefs<double>(kappa, mu, cf[0], cb[0]);
     const double2* const fields[1] = {in + off};
     double2 acc[1][12];
     wilson_site<double, 1>(g, links, fields, cf, cb, site, acc);
@@ -58,9 +66,9 @@ __global__ __launch_bounds__(ENT) void eig_apply(Geom g, const double2* __restri
     }
 }
 
-// part[(i p + j) nchunk + chunk] = sum over the chunk of conj(X_i) Y_j
+// part[(i q + j) nchunk + chunk] = sum over the chunk of conj(X_i) Y_j
 __global__ __launch_bounds__(GNT) void eig_gram(const double2* __restrict__ X, const double2* __restrict__ Y,
-                                                int p, size_t n, int nchunk, double2* __restrict__ part) {
+                                                int q, size_t n, int nchunk, double2* __restrict__ part) {
     __shared__ double2 lds[GNT / 64];
     const int chunk = blockIdx.x, i = blockIdx.y, j = blockIdx.z;
     const size_t len = (n + nchunk - 1) / nchunk;
@@ -70,313 +78,352 @@ __global__ __launch_bounds__(GNT) void eig_gram(const double2* __restrict__ X, c
     double2 s = mk(0.0, 0.0);
     for (size_t e = lo + threadIdx.x; e < hi; e += GNT) s = cadd(s, cmulc(xi[e], yj[e]));
     s = block_sum<GNT>(s, lds);
-    if (threadIdx.x == 0) part[((size_t)i * p + j) * nchunk + chunk] = s;
+    if (threadIdx.x == 0) part[((size_t)i * q + j) * nchunk + chunk] = s;
 }
 
-// out[q] = sum_c part[q nchunk + c] for q < count (fixed order)
+// out[r] = sum_c part[r nchunk + c] for r < count (fixed order)
 __global__ __launch_bounds__(GNT) void eig_sum(const double2* __restrict__ part, int nchunk, int count,
                                                double2* __restrict__ out) {
     __shared__ double2 lds[GNT / 64];
-    const int q = blockIdx.x;
-    if (q >= count) return;
+    const int r = blockIdx.x;
+    if (r >= count) return;
     double2 s = mk(0.0, 0.0);
-    for (int c = threadIdx.x; c < nchunk; c += GNT) s = cadd(s, part[(size_t)q * nchunk + c]);
+    for (int c = threadIdx.x; c < nchunk; c += GNT) s = cadd(s, part[(size_t)r * nchunk + c]);
     s = block_sum<GNT>(s, lds);
-    if (threadIdx.x == 0) out[q] = s;
+    if (threadIdx.x == 0) out[r] = s;
 }
 
-// out_v = sum_u X_u Z(u, v) (Z column-major, p x p); 8 outputs per thread
-constexpr int ROT = 8;
+// out_v = sum_{u < pin} X_u Z(u, v) for v < qout (Z column-major, pin x qout); ROT outputs per thread
 __global__ __launch_bounds__(GNT) void eig_rotate(const double2* __restrict__ X, const double2* __restrict__ Z,
-                                                  double2* __restrict__ out, int p, size_t n) {
+                                                  double2* __restrict__ out, int pin, int qout, size_t n) {
     const size_t e = (size_t)blockIdx.x * GNT + threadIdx.x;
     if (e >= n) return;
     const int v0 = blockIdx.y * ROT;
     double2 acc[ROT];
 #pragma unroll
     for (int k = 0; k < ROT; ++k) acc[k] = mk(0.0, 0.0);
-    for (int u = 0; u < p; ++u) {
+    for (int u = 0; u < pin; ++u) {
         const double2 x = X[(size_t)u * n + e];
 #pragma unroll
         for (int k = 0; k < ROT; ++k)
-            if (v0 + k < p) acc[k] = cadd(acc[k], cmul(x, Z[(size_t)(v0 + k) * p + u]));
+            if (v0 + k < qout) acc[k] = cadd(acc[k], cmul(x, Z[(size_t)(v0 + k) * pin + u]));
     }
 #pragma unroll
     for (int k = 0; k < ROT; ++k)
-        if (v0 + k < p) out[(size_t)(v0 + k) * n + e] = acc[k];
+        if (v0 + k < qout) out[(size_t)(v0 + k) * n + e] = acc[k];
 }
 
 // part[v nchunk + chunk] = sum over the chunk of |AX_v - theta_v X_v|^2 (in .x)
 __global__ __launch_bounds__(GNT) void eig_resid(const double2* __restrict__ AX, const double2* __restrict__ X,
-                                                 const double* __restrict__ theta, size_t n, int nchunk,
+                                                 const double2* __restrict__ theta, size_t n, int nchunk,
                                                  double2* __restrict__ part) {
     __shared__ double2 lds[GNT / 64];
     const int chunk = blockIdx.x, v = blockIdx.y;
     const size_t len = (n + nchunk - 1) / nchunk;
     const size_t lo = (size_t)chunk * len, hi = (lo + len < n) ? lo + len : n;
-    const double t = theta[v];
+    const double2 t = theta[v];
     double s = 0.0;
-    for (size_t e = lo + threadIdx.x; e < hi; e += GNT) s += cabs2(csub(AX[(size_t)v * n + e], cscale(X[(size_t)v * n + e], t)));
+    for (size_t e = lo + threadIdx.x; e < hi; e += GNT)
+        s += cabs2(csub(AX[(size_t)v * n + e], cmul(t, X[(size_t)v * n + e])));
     const double2 r = block_sum<GNT>(mk(s, 0.0), lds);
     if (threadIdx.x == 0) part[(size_t)v * nchunk + chunk] = r;
 }
 
-using cd = std::complex<double>;
-
-// Lower Cholesky factor of the Hermitian positive definite G (p x p, column-major); false if not PD.
-bool cholesky(std::vector<cd>& G, int p) {
-    for (int j = 0; j < p; ++j) {
-        double d = G[j + (size_t)j * p].real();
-        for (int k = 0; k < j; ++k) d -= std::norm(G[j + (size_t)k * p]);
-        if (!(d > 0.0)) return false;
-        const double ljj = std::sqrt(d);
-        G[j + (size_t)j * p] = ljj;
-        for (int i = j + 1; i < p; ++i) {
-            cd s = G[i + (size_t)j * p];
-            for (int k = 0; k < j; ++k) s -= G[i + (size_t)k * p] * std::conj(G[j + (size_t)k * p]);
-            G[i + (size_t)j * p] = s / ljj;
-        }
-        for (int i = 0; i < j; ++i) G[i + (size_t)j * p] = 0.0;
-    }
-    return true;
-}
-
-// Z = L^{-H} (upper triangular), L lower triangular, both column-major p x p
-std::vector<cd> inverse_adjoint(const std::vector<cd>& L, int p) {
-    // solve L^H Z = I column by column (back substitution)
-    std::vector<cd> Z((size_t)p * p, 0.0);
-    for (int c = 0; c < p; ++c) {
-        for (int i = p - 1; i >= 0; --i) {
-            cd s = (i == c) ? 1.0 : 0.0;
-            for (int k = i + 1; k < p; ++k) s -= std::conj(L[k + (size_t)i * p]) * Z[k + (size_t)c * p];
-            Z[i + (size_t)c * p] = s / std::conj(L[i + (size_t)i * p]);
-        }
-    }
-    return Z;
-}
-
-// Cyclic Jacobi for the Hermitian H (p x p, column-major, overwritten): H = W diag(w) W^H.
-void jacobi(std::vector<cd>& H, int p, std::vector<double>& w, std::vector<cd>& W) {
-    W.assign((size_t)p * p, 0.0);
-    for (int i = 0; i < p; ++i) W[i + (size_t)i * p] = 1.0;
-    auto at = [&](int i, int j) -> cd& { return H[i + (size_t)j * p]; };
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int j = 0; j < p; ++j)
-            for (int i = 0; i < p; ++i) {
-                tot += std::norm(at(i, j));
-                if (i != j) off += std::norm(at(i, j));
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int k = 0; k < p - 1; ++k)
-            for (int l = k + 1; l < p; ++l) {
-                const cd g = at(k, l);
-                const double ag = std::abs(g);
-                if (ag == 0.0) continue;
-                // phase e^{i phi} = g / |g| makes the 2x2 block real: then a real rotation
-                const cd ph = g / ag;
-                const double a = at(k, k).real(), b = at(l, l).real();
-                const double tau = (b - a) / (2.0 * ag);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
-                // U = [[c, s ph], [-s conj(ph), c]] in the (k, l) plane; H <- U^H H U, W <- W U
-                for (int i = 0; i < p; ++i) {   // columns
-                    const cd hik = at(i, k), hil = at(i, l);
-                    at(i, k) = c * hik - s * std::conj(ph) * hil;
-                    at(i, l) = s * ph * hik + c * hil;
-                }
-                for (int j = 0; j < p; ++j) {   // rows
-                    const cd hkj = at(k, j), hlj = at(l, j);
-                    at(k, j) = c * hkj - s * ph * hlj;
-                    at(l, j) = s * std::conj(ph) * hkj + c * hlj;
-                }
-                at(k, l) = 0.0;
-                at(l, k) = 0.0;
-                for (int i = 0; i < p; ++i) {
-                    const cd wik = W[i + (size_t)k * p], wil = W[i + (size_t)l * p];
-                    W[i + (size_t)k * p] = c * wik - s * std::conj(ph) * wil;
-                    W[i + (size_t)l * p] = s * ph * wik + c * wil;
-                }
-            }
-    }
-    w.resize(p);
-    for (int i = 0; i < p; ++i) w[i] = at(i, i).real();
-}
+using dense::cd;
+using dense::Mat;
 
 struct Dev {
     double2 *X = nullptr, *Y = nullptr, *T = nullptr, *U = nullptr, *part = nullptr, *small = nullptr;
-    double* theta = nullptr;
+    double2* theta = nullptr;
     ~Dev() {
         for (void* q : {(void*)X, (void*)Y, (void*)T, (void*)U, (void*)part, (void*)small, (void*)theta})
             if (q) (void)hipFree(q);
     }
 };
 
-}  // namespace
-
-// (H + H^H) / 2 in place (rounding of a Hermitian Gram matrix)
-static void symmetrise(std::vector<cd>& H, int p) {
-    for (int j = 0; j < p; ++j)
-        for (int i = 0; i < j; ++i) {
-            const cd v = 0.5 * (H[i + (size_t)j * p] + std::conj(H[j + (size_t)i * p]));
-            H[i + (size_t)j * p] = v;
-            H[j + (size_t)i * p] = std::conj(v);
-        }
-    for (int i = 0; i < p; ++i) H[i + (size_t)i * p] = H[i + (size_t)i * p].real();
-}
-
-// Gram matrix out = X^H Y of the first p vectors (column-major on the host: out[i + j p] = X_i^H Y_j)
-static int gram(const double2* X, const double2* Y, int p, size_t n, Dev& d, int nchunk, std::vector<cd>& out) {
-    hipLaunchKernelGGL(eig_gram, dim3(nchunk, p, p), dim3(GNT), 0, nullptr, X, Y, p, n, nchunk, d.part);
-    hipLaunchKernelGGL(eig_sum, dim3(p * p), dim3(GNT), 0, nullptr, d.part, nchunk, p * p, d.small);
-    std::vector<double2> h((size_t)p * p);
-    if (hipMemcpy(h.data(), d.small, sizeof(double2) * p * p, hipMemcpyDeviceToHost) != hipSuccess) return 1;
-    out.resize((size_t)p * p);
-    for (int i = 0; i < p; ++i)
-        for (int j = 0; j < p; ++j) out[i + (size_t)j * p] = cd(h[(size_t)i * p + j].x, h[(size_t)i * p + j].y);
-    return 0;
-}
-
-static int rotate(const double2* X, const std::vector<cd>& Z, double2* out, int p, size_t n, Dev& d) {
-    std::vector<double2> h((size_t)p * p);
-    for (size_t q = 0; q < h.size(); ++q) h[q] = mk(Z[q].real(), Z[q].imag());
-    if (hipMemcpy(d.small, h.data(), sizeof(double2) * p * p, hipMemcpyHostToDevice) != hipSuccess) return 1;
-    hipLaunchKernelGGL(eig_rotate, dim3((unsigned)((n + GNT - 1) / GNT), (p + ROT - 1) / ROT), dim3(GNT), 0, nullptr, X,
-                       d.small, out, p, n);
-    return hipGetLastError() == hipSuccess ? 0 : 1;
-}
-
-int eig_chfsi(const Geom& g, const double2* links, double kappa, int m, int p, int degree, int max_iter, double tol,
-              unsigned long long seed, double2* vecs_out, double* lambda_out, double* resid_out, int* iters_out,
-              std::string& err) {
-    const size_t n = (size_t)12 * g.V;
-    const int nb = (g.V + ENT - 1) / ENT;
-    const int nchunk = (int)std::min<size_t>(64, (n + 4095) / 4096);
+// One lattice's device side: the operator A(mu), launch shapes and the block buffers.
+struct Run {
+    Geom g;
+    const double2* links = nullptr;
+    double kappa = 0.0, mu = 0.0;
+    size_t n = 0;
+    int nb = 0, nchunk = 0, p = 0;
     Dev d;
-    const size_t blk = sizeof(double2) * n * p;
-    if (hipMalloc(&d.X, blk) || hipMalloc(&d.Y, blk) || hipMalloc(&d.T, blk) || hipMalloc(&d.U, blk) ||
-        hipMalloc(&d.part, sizeof(double2) * (size_t)p * p * nchunk) || hipMalloc(&d.small, sizeof(double2) * p * p) ||
-        hipMalloc(&d.theta, sizeof(double) * p)) {
-        err = "eigensolver: device allocation failed";
-        return NKS_E_NOMEM;
+
+    void apply(const double2* in, double2* out, int count, double alpha = 1.0, const double2* y = nullptr,
+               double beta = 0.0, const double2* z = nullptr, double gamma = 0.0) {
+        hipLaunchKernelGGL(eig_apply, dim3(nb, count), dim3(ENT), 0, nullptr, g, links, kappa, mu, in, out, alpha, y,
+                           beta, z, gamma);
     }
+    // out = X^H Y of the first q vectors (host, column-major: out[i + j q] = X_i^H Y_j)
+    bool gram(const double2* X, const double2* Y, int q, Mat& out) {
+        hipLaunchKernelGGL(eig_gram, dim3(nchunk, q, q), dim3(GNT), 0, nullptr, X, Y, q, n, nchunk, d.part);
+        hipLaunchKernelGGL(eig_sum, dim3(q * q), dim3(GNT), 0, nullptr, d.part, nchunk, q * q, d.small);
+        std::vector<double2> h((size_t)q * q);
+        if (hipMemcpy(h.data(), d.small, sizeof(double2) * q * q, hipMemcpyDeviceToHost) != hipSuccess) return false;
+        out.resize((size_t)q * q);
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) out[i + (size_t)j * q] = cd(h[(size_t)i * q + j].x, h[(size_t)i * q + j].y);
+        return true;
+    }
+    // out_v = sum_{u < pin} X_u Z(u, v) for v < qout
+    bool rotate(const double2* X, const Mat& Z, double2* out, int pin, int qout) {
+        std::vector<double2> h((size_t)pin * qout);
+        for (size_t r = 0; r < h.size(); ++r) h[r] = mk(Z[r].real(), Z[r].imag());
+        if (hipMemcpy(d.small, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice) != hipSuccess) return false;
+        hipLaunchKernelGGL(eig_rotate, dim3((unsigned)((n + GNT - 1) / GNT), (qout + ROT - 1) / ROT), dim3(GNT), 0,
+                           nullptr, X, d.small, out, pin, qout, n);
+        return hipGetLastError() == hipSuccess;
+    }
+    // X <- X L^{-H} with X^H X = L L^H, twice
+    int orthonormalise(std::string& err) {
+        Mat G;
+        for (int pass = 0; pass < 2; ++pass) {
+            if (!gram(d.X, d.X, p, G)) { err = "eigensolver: gram"; return NKS_E_HIP; }
+            if (!dense::cholesky(G, p)) { err = "eigensolver: block lost rank (Cholesky of X^H X failed)"; return NKS_E_NOCONV; }
+            if (!rotate(d.X, dense::inverse_adjoint(G, p), d.Y, p, p)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
+            std::swap(d.X, d.Y);
+        }
+        return NKS_OK;
+    }
+    // X <- T_deg(A^2) X, the Chebyshev filter on [a, b] scaled to 1 at a0 (three-term recurrence)
+    bool filter(int deg, double a, double b, double a0) {
+        const double e = (b - a) / 2.0, c = (b + a) / 2.0;
+        double sigma = e / (a0 - c);
+        const double tau = 2.0 / sigma;
+        apply(d.X, d.T, p);
+        apply(d.T, d.Y, p, sigma / e, d.X, -c * sigma / e);
+        double2 *Xp = d.X, *Yc = d.Y, *Yn = d.U;
+        for (int i = 2; i <= deg; ++i) {
+            const double sigma2 = 1.0 / (tau - sigma);
+            apply(Yc, d.T, p);
+            apply(d.T, Yn, p, 2.0 * sigma2 / e, Yc, -2.0 * c * sigma2 / e, Xp, -sigma * sigma2);
+            double2* t = Xp;
+            Xp = Yc;
+            Yc = Yn;
+            Yn = t;
+            sigma = sigma2;
+        }
+        if (Yc != d.X) {   // the filtered block becomes X; the buffers keep their roles
+            double2* old_x = d.X;
+            d.X = Yc;
+            if (d.Y == Yc) d.Y = old_x;
+            else d.U = old_x;
+        }
+        return hipGetLastError() == hipSuccess;
+    }
+};
+
+// Indices 0..q-1 in ascending order of key (stable)
+template <typename F>
+std::vector<int> order_by(int q, F key) {
+    std::vector<int> o(q);
+    for (int i = 0; i < q; ++i) o[i] = i;
+    std::stable_sort(o.begin(), o.end(), [&](int x, int y) { return key(x) < key(y); });
+    return o;
+}
+
+// Columns of W (q x q) in the order o
+Mat permute_columns(const Mat& W, int q, const std::vector<int>& o) {
+    Mat out((size_t)q * q);
+    for (int j = 0; j < q; ++j)
+        for (int i = 0; i < q; ++i) out[i + (size_t)j * q] = W[i + (size_t)o[j] * q];
+    return out;
+}
+
+// One subspace iteration run on A(R.mu) from a seeded start block: m eigenpairs
+// with eigenvalues ascending in |theta|, unit right eigenvectors in the first m
+// vectors of R.d.Y, residuals in res.
+int solve(Run& R, bool hermitian, int m, int degree, int max_iter, double tol, double bound, unsigned long long seed,
+          std::vector<cd>& theta, std::vector<double>& res, int& it, std::string& err) {
+    const int p = R.p;
+    const size_t n = R.n;
+    Dev& d = R.d;
+    theta.assign(m, 0.0);
+    res.assign(m, INFINITY);
+    it = 0;
     {   // seeded Gaussian start block
         std::mt19937_64 rng(seed);
         std::normal_distribution<double> nd;
         std::vector<double2> h(n * p);
         for (auto& v : h) v = mk(nd(rng), nd(rng));
-        if (hipMemcpy(d.X, h.data(), blk, hipMemcpyHostToDevice) != hipSuccess) { err = "eigensolver: copy"; return NKS_E_HIP; }
+        if (hipMemcpy(d.X, h.data(), sizeof(double2) * n * p, hipMemcpyHostToDevice) != hipSuccess) {
+            err = "eigensolver: copy";
+            return NKS_E_HIP;
+        }
     }
-    // ||A|| <= 1 + 8 sqrt(2) kappa: per direction the two hops map into the
-    // complementary ranges of (1 + gamma)/2 and (1 - gamma)/2, so their sum has norm <= 2 sqrt(2)
-    const double bound = (1.0 + 8.0 * std::sqrt(2.0) * kappa) * (1.0 + 8.0 * std::sqrt(2.0) * kappa);
     double a = bound / 10.0, a0 = 0.0;
-    std::vector<double> theta(m, 0.0), res(m, INFINITY);
-    std::vector<cd> G, H, Hm, W;
-    int it = 0;
-    for (; it < max_iter; ++it) {
-        if (it > 0) {
-            // Chebyshev filter of degree `degree` in A^2 on [a, b], scaled to 1 near a0
-            const double e = (bound - a) / 2.0, c = (bound + a) / 2.0;
-            double sigma = e / (a0 - c);
-            const double tau = 2.0 / sigma;
-            // Y = (A^2 X - c X) sigma / e
-            hipLaunchKernelGGL(eig_apply, dim3(nb, p), dim3(ENT), 0, nullptr, g, links, kappa, d.X, d.T, 1.0,
-                               (const double2*)nullptr, 0.0, (const double2*)nullptr, 0.0);
-            hipLaunchKernelGGL(eig_apply, dim3(nb, p), dim3(ENT), 0, nullptr, g, links, kappa, d.T, d.Y, sigma / e,
-                               (const double2*)d.X, -c * sigma / e, (const double2*)nullptr, 0.0);
-            double2 *Xp = d.X, *Yc = d.Y, *Yn = d.U;
-            for (int i = 2; i <= degree; ++i) {
-                const double sigma2 = 1.0 / (tau - sigma);
-                hipLaunchKernelGGL(eig_apply, dim3(nb, p), dim3(ENT), 0, nullptr, g, links, kappa, Yc, d.T, 1.0,
-                                   (const double2*)nullptr, 0.0, (const double2*)nullptr, 0.0);
-                hipLaunchKernelGGL(eig_apply, dim3(nb, p), dim3(ENT), 0, nullptr, g, links, kappa, d.T, Yn,
-                                   2.0 * sigma2 / e, (const double2*)Yc, -2.0 * c * sigma2 / e, (const double2*)Xp,
-                                   -sigma * sigma2);
-                double2* t = Xp;
-                Xp = Yc;
-                Yc = Yn;
-                Yn = t;
-                sigma = sigma2;
-            }
-            if (Yc != d.X) {
-                // the filtered block becomes X (buffers keep their roles by swapping pointers)
-                double2* old_x = d.X;
-                d.X = Yc;
-                if (d.Y == Yc) d.Y = old_x;
-                else if (d.U == Yc) d.U = old_x;
-            }
-            if (hipGetLastError() != hipSuccess) { err = "eigensolver: filter launch"; return NKS_E_HIP; }
-        }
-        // orthonormalise twice: X <- X L^{-H} with G = X^H X = L L^H
-        for (int pass = 0; pass < 2; ++pass) {
-            if (gram(d.X, d.X, p, n, d, nchunk, G)) { err = "eigensolver: gram"; return NKS_E_HIP; }
-            if (!cholesky(G, p)) { err = "eigensolver: block lost rank (Cholesky of X^H X failed)"; return NKS_E_NOCONV; }
-            if (rotate(d.X, inverse_adjoint(G, p), d.Y, p, n, d)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
+    Mat H, W;
+    while (it < max_iter) {
+        if (it > 0 && !R.filter(degree, a, bound, a0)) { err = "eigensolver: filter launch"; return NKS_E_HIP; }
+        ++it;
+        int rc = R.orthonormalise(err);
+        if (rc != NKS_OK) return rc;
+        // order the block by |theta^2| (Rayleigh-Ritz on A^2); T = A X after this step
+        std::vector<double> t2(p);
+        R.apply(d.X, d.T, p);
+        if (hermitian) {
+            if (!R.gram(d.T, d.T, p, H)) { err = "eigensolver: gram"; return NKS_E_HIP; }
+            dense::symmetrise(H, p);
+            std::vector<double> w;
+            dense::jacobi(H, p, w, W);
+            const std::vector<int> o = order_by(p, [&](int i) { return w[i]; });
+            for (int j = 0; j < p; ++j) t2[j] = w[o[j]];
+            const Mat Wo = permute_columns(W, p, o);
+            if (!R.rotate(d.X, Wo, d.Y, p, p) || !R.rotate(d.T, Wo, d.U, p, p)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
             std::swap(d.X, d.Y);
+            std::swap(d.T, d.U);
+        } else {
+            R.apply(d.T, d.U, p);   // A^2 X
+            if (!R.gram(d.X, d.U, p, H)) { err = "eigensolver: gram"; return NKS_E_HIP; }
+            std::vector<cd> lam;
+            if (!dense::eig_general(H, p, lam, W)) { err = "eigensolver: QR of the Ritz matrix of A^2"; return NKS_E_NOCONV; }
+            const std::vector<int> o = order_by(p, [&](int i) { return std::abs(lam[i]); });
+            for (int j = 0; j < p; ++j) t2[j] = std::abs(lam[o[j]]);
+            if (!R.rotate(d.X, permute_columns(W, p, o), d.Y, p, p)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
+            std::swap(d.X, d.Y);
+            rc = R.orthonormalise(err);
+            if (rc != NKS_OK) return rc;
+            R.apply(d.X, d.T, m);
         }
-        // Rayleigh-Ritz on A^2 (extremal, no spurious interior values): H2 = (AX)^H (AX)
-        hipLaunchKernelGGL(eig_apply, dim3(nb, p), dim3(ENT), 0, nullptr, g, links, kappa, d.X, d.T, 1.0,
-                           (const double2*)nullptr, 0.0, (const double2*)nullptr, 0.0);
-        if (gram(d.T, d.T, p, n, d, nchunk, H)) { err = "eigensolver: gram"; return NKS_E_HIP; }
-        symmetrise(H, p);
-        std::vector<double> w2;
-        jacobi(H, p, w2, W);
-        std::vector<int> ord(p);
-        for (int i = 0; i < p; ++i) ord[i] = i;
-        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return w2[x] < w2[y]; });
-        std::vector<cd> Wo((size_t)p * p);
-        for (int j = 0; j < p; ++j)
-            for (int i = 0; i < p; ++i) Wo[i + (size_t)j * p] = W[i + (size_t)ord[j] * p];
-        if (rotate(d.X, Wo, d.Y, p, n, d) || rotate(d.T, Wo, d.U, p, n, d)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
-        std::swap(d.X, d.Y);
-        std::swap(d.T, d.U);
-        // next filter interval: damp [largest squared Ritz value of the block, b]
-        a = std::min(w2[ord[p - 1]], bound / 2.0);
-        a0 = std::max(w2[ord[0]], 0.0);
-        // Rayleigh-Ritz on A within the m vectors of the smallest squared Ritz
-        // values: the eigenpairs and their residuals (into Y, U: m vectors)
-        if (gram(d.X, d.T, m, n, d, nchunk, Hm)) { err = "eigensolver: gram"; return NKS_E_HIP; }
-        symmetrise(Hm, m);
-        std::vector<double> wa;
-        jacobi(Hm, m, wa, W);
-        std::vector<int> om(m);
-        for (int i = 0; i < m; ++i) om[i] = i;
-        std::stable_sort(om.begin(), om.end(), [&](int x, int y) { return std::fabs(wa[x]) < std::fabs(wa[y]); });
-        std::vector<cd> Wm((size_t)m * m);
-        theta.resize(m);
+        // next filter interval: damp [largest |theta^2| of the block, b]
+        a = std::min(t2[p - 1], bound / 2.0);
+        a0 = std::max(t2[0], 0.0);
+        // Rayleigh-Ritz on A within the first m vectors: eigenpairs into Y, A Y into U
+        if (!R.gram(d.X, d.T, m, H)) { err = "eigensolver: gram"; return NKS_E_HIP; }
+        std::vector<cd> lam(m);
+        if (hermitian) {
+            dense::symmetrise(H, m);
+            std::vector<double> w;
+            dense::jacobi(H, m, w, W);
+            for (int i = 0; i < m; ++i) lam[i] = w[i];
+        } else if (!dense::eig_general(H, m, lam, W)) {
+            err = "eigensolver: QR of the Ritz matrix of A";
+            return NKS_E_NOCONV;
+        }
+        const std::vector<int> o = order_by(m, [&](int i) { return std::abs(lam[i]); });
+        std::vector<double2> th(m);
         for (int j = 0; j < m; ++j) {
-            theta[j] = wa[om[j]];
-            for (int i = 0; i < m; ++i) Wm[i + (size_t)j * m] = W[i + (size_t)om[j] * m];
+            theta[j] = lam[o[j]];
+            th[j] = mk(theta[j].real(), theta[j].imag());
         }
-        if (rotate(d.X, Wm, d.Y, m, n, d) || rotate(d.T, Wm, d.U, m, n, d)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
-        if (hipMemcpy(d.theta, theta.data(), sizeof(double) * m, hipMemcpyHostToDevice) != hipSuccess) { err = "copy"; return NKS_E_HIP; }
-        hipLaunchKernelGGL(eig_resid, dim3(nchunk, m), dim3(GNT), 0, nullptr, d.U, d.Y, d.theta, n, nchunk, d.part);
-        hipLaunchKernelGGL(eig_sum, dim3(m), dim3(GNT), 0, nullptr, d.part, nchunk, m, d.small);
+        const Mat Wm = permute_columns(W, m, o);
+        if (!R.rotate(d.X, Wm, d.Y, m, m) || !R.rotate(d.T, Wm, d.U, m, m)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
+        if (hipMemcpy(d.theta, th.data(), sizeof(double2) * m, hipMemcpyHostToDevice) != hipSuccess) {
+            err = "eigensolver: copy";
+            return NKS_E_HIP;
+        }
+        hipLaunchKernelGGL(eig_resid, dim3(R.nchunk, m), dim3(GNT), 0, nullptr, d.U, d.Y, d.theta, n, R.nchunk, d.part);
+        hipLaunchKernelGGL(eig_sum, dim3(m), dim3(GNT), 0, nullptr, d.part, R.nchunk, m, d.small);
         std::vector<double2> hr(m);
-        if (hipMemcpy(hr.data(), d.small, sizeof(double2) * m, hipMemcpyDeviceToHost) != hipSuccess) { err = "copy"; return NKS_E_HIP; }
+        if (hipMemcpy(hr.data(), d.small, sizeof(double2) * m, hipMemcpyDeviceToHost) != hipSuccess) {
+            err = "eigensolver: copy";
+            return NKS_E_HIP;
+        }
         double worst = 0.0;
         for (int i = 0; i < m; ++i) {
             res[i] = std::sqrt(hr[i].x);
             worst = std::max(worst, res[i]);
         }
-        if (worst <= tol) { ++it; break; }
+        if (worst <= tol) return NKS_OK;
     }
+    err = "eigensolver: residual above tol after max_iter iterations";
+    return NKS_E_NOCONV;
+}
+
+}  // namespace
+
+int eig_chfsi(const Geom& g, const double2* links, double kappa, double mu, int m, int p, int degree, int max_iter,
+              double tol, unsigned long long seed, double2* rvecs_out, double2* lvecs_out, double* lambda_out,
+              double* resid_out, int* iters_out, std::string& err) {
+    Run R;
+    R.g = g;
+    R.links = links;
+    R.kappa = kappa;
+    R.mu = mu;
+    R.n = (size_t)12 * g.V;
+    R.nb = (g.V + ENT - 1) / ENT;
+    R.nchunk = (int)std::min<size_t>(64, (R.n + 4095) / 4096);
+    R.p = p;
+    Dev& d = R.d;
+    const size_t n = R.n, blk = sizeof(double2) * n * p;
+    if (hipMalloc(&d.X, blk) || hipMalloc(&d.Y, blk) || hipMalloc(&d.T, blk) || hipMalloc(&d.U, blk) ||
+        hipMalloc(&d.part, sizeof(double2) * (size_t)p * p * R.nchunk) ||
+        hipMalloc(&d.small, sizeof(double2) * p * p) || hipMalloc(&d.theta, sizeof(double2) * p)) {
+        err = "eigensolver: device allocation failed";
+        return NKS_E_NOMEM;
+    }
+    // ||A|| <= 1 + kappa (6 sqrt(2) + 2 sqrt(2 cosh 2mu)): per direction the two hops
+    // land in the complementary ranges of (1 - gamma)/2 and (1 + gamma)/2, so their sum
+    // has norm <= 2 sqrt(c_+^2 + c_-^2) for hop factors c_+, c_- (1, or e^{+mu}, e^{-mu} in t)
+    const double na = 1.0 + kappa * (6.0 * std::sqrt(2.0) + 2.0 * std::sqrt(2.0 * std::cosh(2.0 * mu)));
+    const double bound = na * na;
+    const bool hermitian = mu == 0.0;
+    std::vector<cd> th;
+    std::vector<double> res;
+    int it = 0;
+    int rc = solve(R, hermitian, m, degree, max_iter, tol, bound, seed, th, res, it, err);
     if (iters_out) *iters_out = it;
-    for (int i = 0; i < m; ++i) {
-        if (lambda_out) lambda_out[i] = theta[i];
-        if (resid_out) resid_out[i] = res[i];
-    }
-    if (hipMemcpy(vecs_out, d.Y, sizeof(double2) * n * m, hipMemcpyDeviceToDevice) != hipSuccess) {
+    auto report = [&](const std::vector<double>& r) {
+        for (int i = 0; i < m; ++i) {
+            if (lambda_out) {
+                lambda_out[2 * i] = th[i].real();
+                lambda_out[2 * i + 1] = th[i].imag();
+            }
+            if (resid_out) resid_out[i] = r[i];
+        }
+    };
+    report(res);
+    if (rc != NKS_OK) return rc;
+    if (hipMemcpy(rvecs_out, d.Y, sizeof(double2) * n * m, hipMemcpyDeviceToDevice) != hipSuccess) {
         err = "eigensolver: copy out";
         return NKS_E_HIP;
     }
-    double worst = 0.0;
-    for (int i = 0; i < m; ++i) worst = std::max(worst, res[i]);
-    if (!(worst <= tol)) {
-        err = "eigensolver: residual above tol after max_iter iterations";
-        return NKS_E_NOCONV;
+    if (hermitian) {
+        if (hipMemcpy(lvecs_out, d.Y, sizeof(double2) * n * m, hipMemcpyDeviceToDevice) != hipSuccess) {
+            err = "eigensolver: copy out";
+            return NKS_E_HIP;
+        }
+        return NKS_OK;
     }
+    // left eigenvectors: the right eigenvectors of A(-mu) = A^dagger, eigenvalues conj(lambda)
+    R.mu = -mu;
+    std::vector<cd> thl;
+    std::vector<double> resl;
+    int itl = 0;
+    rc = solve(R, false, m, degree, max_iter, tol, bound, seed + 1, thl, resl, itl, err);
+    if (iters_out) *iters_out = it + itl;
+    for (int i = 0; i < m; ++i) resl[i] = std::max(res[i], resl[i]);
+    report(resl);
+    if (rc != NKS_OK) return rc;
+    // pair l_j with r_i where conj(theta_l_j) = theta_i, then l_i = l_j / conj(l_j^H r_i)
+    Mat C;   // C(j, i) = l_j^H r_i
+    if (!R.gram(d.Y, rvecs_out, m, C)) { err = "eigensolver: gram"; return NKS_E_HIP; }
+    Mat Z((size_t)m * m, 0.0);
+    std::vector<bool> used(m, false);
+    for (int i = 0; i < m; ++i) {
+        int best = -1;
+        double bd = INFINITY;
+        for (int j = 0; j < m; ++j) {
+            const double dd = std::abs(std::conj(thl[j]) - th[i]);
+            if (!used[j] && dd < bd) {
+                bd = dd;
+                best = j;
+            }
+        }
+        if (best < 0 || bd > 1e-6 * std::max(1.0, std::abs(th[i]))) {
+            err = "eigensolver: the left and right eigenvalues do not pair up (tie at the m-th |lambda|?)";
+            return NKS_E_NOCONV;
+        }
+        used[best] = true;
+        const cd s = C[best + (size_t)i * m];
+        if (!(std::abs(s) > 0.0)) {
+            err = "eigensolver: l^dagger r = 0 for a computed pair";
+            return NKS_E_NOCONV;
+        }
+        Z[best + (size_t)i * m] = 1.0 / std::conj(s);
+    }
+    if (!R.rotate(d.Y, Z, lvecs_out, m, m)) { err = "eigensolver: rotate"; return NKS_E_HIP; }
     return NKS_OK;
 }
 

@@ -333,11 +333,13 @@ void launch_predict(JobDesc* jobs, int njobs, int j, hipStream_t s);      // aft
 void launch_label(JobDesc* jobs, int njobs, hipStream_t s);               // after the outer loop
 size_t nest_words(int k, int ell, int levels, const int* ell_deep);
 
-// eig.hip: m eigenpairs of the Hermitian A with the smallest |lambda| by a
-// block of p >= m vectors; the eigenvectors go to vecs_out (SoA [i][comp][site]).
-int eig_chfsi(const Geom& g, const double2* links, double kappa, int m, int p, int degree, int max_iter, double tol,
-              unsigned long long seed, double2* vecs_out, double* lambda_out, double* resid_out, int* iters_out,
-              std::string& err);
+// eig.hip: m eigenpairs of A(mu) with the smallest |lambda| by a block of
+// p >= m vectors: unit right eigenvectors to rvecs_out, left eigenvectors with
+// l_i^H r_i = 1 to lvecs_out (both SoA [i][comp][site]; equal for mu = 0),
+// eigenvalues as (re, im) pairs to lambda_out.
+int eig_chfsi(const Geom& g, const double2* links, double kappa, double mu, int m, int p, int degree, int max_iter,
+              double tol, unsigned long long seed, double2* rvecs_out, double2* lvecs_out, double* lambda_out,
+              double* resid_out, int* iters_out, std::string& err);
 
 // mlp.hip
 int mlp_nparams();

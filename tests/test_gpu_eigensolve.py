@@ -1,8 +1,9 @@
-"""GPU eigensolver for the deflation eigenpairs (nks_lattice_eigensolve,
-Hermitian A): eigenvalues and eigenvectors against the oracle's dense
-eigendecomposition, residuals recomputed with the oracle's operator, the
-installed pairs in a deflated sign application against the oracle's
-deflated method, and the error paths."""
+"""GPU eigensolver for the deflation eigenpairs (nks_lattice_eigensolve):
+eigenvalues and eigenvectors against the oracle's dense eigendecomposition
+(Hermitian A at mu = 0; right and left eigenvectors of the non-Hermitian A at
+mu != 0), residuals recomputed with the oracle's operator, the installed
+pairs in a deflated sign application against the oracle's deflated method,
+and the error paths."""
 import numpy as np
 import pytest
 
@@ -12,6 +13,21 @@ from gpu_common import ctx, lattice, operator, rel, to_np
 pytestmark = pytest.mark.gpu
 
 DIMS = (4, 4, 4, 4)
+
+
+def check_biorthonormal(r, l, lam, res):
+    """l_i^dagger r_i = 1 by construction; for i != j,
+    (lambda_i - lambda_j) l_i^dagger r_j = l_i^dagger e_j - f_i^dagger r_j with
+    the right and left residual vectors e_j, f_i (|f_i| <= |l_i| res for the
+    unit left vector), so |l_i^dagger r_j| <= 2 |l_i| res / |lambda_i - lambda_j|."""
+    C = l.conj() @ r.T
+    m = len(lam)
+    assert np.abs(np.diag(C) - 1).max() <= 1e-12
+    for i in range(m):
+        for j in range(m):
+            if i != j:
+                bound = 2 * np.linalg.norm(l[i]) * res.max() / abs(lam[i] - lam[j]) + 1e-13
+                assert abs(C[i, j]) <= bound, (i, j, abs(C[i, j]), bound)
 
 
 def test_eigenpairs_match_dense_eigendecomposition():
@@ -28,6 +44,8 @@ def test_eigenpairs_match_dense_eigendecomposition():
     lam_ref, r_ref, _ = deflation.eigenpairs_smallest(op, m)
     print(f"{it} iterations, worst residual {res.max():.1e}")
     assert np.all(res <= 1e-10) and it >= 1
+    assert np.all(lam.imag == 0)
+    lam = lam.real
     assert np.all(np.diff(np.abs(lam)) >= 0)
     order = np.argsort(np.abs(lam_ref))
     assert np.allclose(lam, np.real(lam_ref[order]), rtol=0, atol=1e-9)
@@ -74,6 +92,7 @@ def test_eigensolve_residuals_with_the_oracle_operator(dims, eps, seed, m):
         r = to_np(r)
     finally:
         lat.set_deflation(None, [])
+    lam = lam.real
     print(f"{dims}: {it} iterations, |lambda| {np.abs(lam).min():.4f}..{np.abs(lam).max():.4f}")
     for i in range(m):
         assert np.linalg.norm(op.matvec(r[i]) - lam[i] * r[i]) <= 2e-10
@@ -82,10 +101,6 @@ def test_eigensolve_residuals_with_the_oracle_operator(dims, eps, seed, m):
 
 def test_eigensolve_errors():
     import paper_0912_4457_amd as nks
-    lat2 = lattice(DIMS, 0.5, 4401, 0.3)
-    with pytest.raises(nks.NKSError) as e:
-        lat2.compute_deflation(4)
-    assert e.value.code == 4
     lat = lattice(DIMS, 0.5, 4401, 0.0)
     for m in (0, 65):
         with pytest.raises(nks.NKSError) as e:
@@ -110,4 +125,77 @@ def test_sign_of_computed_eigenvectors():
     for i in range(4):
         x, st = nks.sign_apply(lat, r[i].clone(), k=300, ell=80)
         assert st["status"] == 0
-        assert rel(to_np(x), np.sign(lam[i]) * to_np(r[i])) <= 1e-9
+        assert rel(to_np(x), np.sign(lam[i].real) * to_np(r[i])) <= 1e-9
+
+
+@pytest.mark.parametrize("mu,m", [(0.3, 8), (0.2, 12)])
+def test_nonhermitian_eigenpairs_match_dense_eigendecomposition(mu, m):
+    # mu != 0: right eigenvectors of A, left ones from A(-mu) = A^dagger,
+    # l_i^dagger r_j = delta_ij (App. C step 1 with the two-sided projection)
+    from oracle import deflation
+    lat = lattice(DIMS, 0.5, 4401, mu)
+    op = operator(DIMS, 0.5, 4401, mu)
+    try:
+        lam, res, it = lat.compute_deflation(m, tol=1e-10)
+        r, l = lat.deflation_vectors()
+        r, l = to_np(r), to_np(l)
+    finally:
+        lat.set_deflation(None, [])
+    lam_ref, r_ref, l_ref = deflation.eigenpairs_smallest(op, m)
+    print(f"mu={mu}: {it} iterations (both runs), worst residual {res.max():.1e}, "
+          f"max |Im lambda| {np.abs(lam.imag).max():.2e}")
+    assert np.all(res <= 1e-10)
+    assert np.all(np.diff(np.abs(lam)) >= 0)
+    assert np.abs(lam.imag).max() > 1e-6           # genuinely non-Hermitian
+    order = np.argsort(np.abs(lam_ref))
+    assert np.allclose(lam, lam_ref[order], rtol=0, atol=1e-9)
+    A = op.dense()
+    for i in range(m):
+        assert abs(np.linalg.norm(r[i]) - 1) <= 1e-12
+        assert np.linalg.norm(A @ r[i] - lam[i] * r[i]) <= 2e-10
+        # l_i is a left eigenvector: l_i^dagger A = lambda_i l_i^dagger
+        assert np.linalg.norm(A.conj().T @ l[i] - np.conj(lam[i]) * l[i]) <= 2e-10 * np.linalg.norm(l[i])
+        rr = r_ref[order[i]] / np.linalg.norm(r_ref[order[i]])
+        assert np.sqrt(max(0.0, 1 - abs(np.vdot(rr, r[i])) ** 2)) <= 1e-6
+        ll = l_ref[order[i]] / np.linalg.norm(l_ref[order[i]])
+        assert np.sqrt(max(0.0, 1 - abs(np.vdot(ll, l[i])) ** 2 / np.vdot(l[i], l[i]).real)) <= 1e-6
+    check_biorthonormal(r, l, lam, res)
+
+
+def test_nonhermitian_pairs_deflate_like_the_oracle():
+    import paper_0912_4457_amd as nks
+    from oracle import deflation, nested
+    mu = 0.3
+    lat = lattice(DIMS, 0.5, 4401, mu)
+    op = operator(DIMS, 0.5, 4401, mu)
+    b = I.gaussian_source(DIMS, 4403).ravel()
+    m = 12
+    lam_ref, r_ref, l_ref = deflation.eigenpairs_smallest(op, m)
+    xm, _ = deflation.project(b, r_ref, l_ref)
+    _, info = nested.sign_apply(op, xm, 100, 30)
+    ref, _ = deflation.sign_apply_deflated(op, b, 100, 30, r_ref, l_ref, lam_ref, p=info["p"])
+    try:
+        lat.compute_deflation(m, tol=1e-11)
+        x, st = nks.sign_apply(lat, b, k=100, ell=30, p=info["p"], deflate=True)
+    finally:
+        lat.set_deflation(None, [])
+    assert st["status"] == 0
+    assert rel(to_np(x), ref) <= 1e-7
+
+
+def test_nonhermitian_eigensolve_residuals_at_8x4():
+    # right and left residuals recomputed with the oracle's operator and its adjoint
+    dims, eps, seed, mu, m = (8, 8, 8, 8), 0.4, 8401, 0.2, 8
+    lat = lattice(dims, eps, seed, mu)
+    op = operator(dims, eps, seed, mu)
+    try:
+        lam, res, it = lat.compute_deflation(m, max_iter=400, tol=1e-10)
+        r, l = lat.deflation_vectors()
+        r, l = to_np(r), to_np(l)
+    finally:
+        lat.set_deflation(None, [])
+    print(f"{dims} mu={mu}: {it} iterations, |lambda| {np.abs(lam).min():.4f}..{np.abs(lam).max():.4f}")
+    for i in range(m):
+        assert np.linalg.norm(op.matvec(r[i]) - lam[i] * r[i]) <= 2e-10
+        assert np.linalg.norm(op.rmatvec(l[i]) - np.conj(lam[i]) * l[i]) <= 2e-10 * np.linalg.norm(l[i])
+    check_biorthonormal(r, l, lam, res)

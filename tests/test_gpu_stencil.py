@@ -55,3 +55,23 @@ def test_stencil_point_source_sparsity():
     y = to_np(nks.apply_op(lat, b)).reshape(-1, 12)
     nz = np.nonzero(np.abs(y).sum(axis=1))[0]
     assert len(nz) == 9
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "u3_phase"])
+def test_stencil_with_general_links(kind):
+    # the stencil takes the links as given: no SU(3) structure is assumed
+    import paper_0912_4457_amd as nks
+    from oracle import dirac
+    from gpu_common import ctx, M0
+    dims = (4, 4, 4, 4)
+    if kind == "gaussian":
+        rng = np.random.default_rng(82)
+        u = (rng.standard_normal(dims + (4, 3, 3)) + 1j * rng.standard_normal(dims + (4, 3, 3))) / 3
+    else:
+        u = I.su3_links(dims, 0.5, 83) * np.exp(0.4j)      # unitary, det = e^{1.2 i}
+    lat = nks.Lattice(ctx(), dims, u, m0=M0, mu=0.1)
+    op = dirac.Operator(u, dims, M0, 0.1)
+    v = I.gaussian_source(dims, 10).ravel()
+    y = to_np(nks.apply_op(lat, v))
+    assert rel(y, op.A @ v) <= 1e-14
+    lat.close()
