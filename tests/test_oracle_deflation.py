@@ -42,3 +42,20 @@ def test_deflation_speeds_up_convergence():
     e0 = np.linalg.norm(y0.ravel() - ref.ravel()) / np.linalg.norm(ref)
     e1 = np.linalg.norm(y1 - ref.ravel()) / np.linalg.norm(ref)
     assert e1 < 0.1 * e0
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_eigenpairs_satisfy_both_eigen_equations(mu):
+    # A r_i = lambda_i r_i and l_i^dagger A = lambda_i l_i^dagger, ascending |lambda|;
+    # real spectrum for the Hermitian A (mu = 0), a complex one otherwise
+    op = _op(mu, dims=(3, 3, 3, 3))
+    lam, r, l = deflation.eigenpairs_smallest(op, 10)
+    A = op.dense()
+    for i in range(10):
+        assert np.linalg.norm(A @ r[i] - lam[i] * r[i]) <= 1e-12 * np.linalg.norm(r[i])
+        assert np.linalg.norm(l[i].conj() @ A - lam[i] * l[i].conj()) <= 1e-12 * np.linalg.norm(l[i])
+    assert np.all(np.diff(np.abs(lam)) >= 0)
+    if mu == 0.0:
+        assert np.abs(lam.imag).max() <= 1e-14
+    else:
+        assert np.abs(lam.imag).max() >= 1e-4
