@@ -28,6 +28,7 @@ constexpr double LUCKY_TAU_HERMITIAN = 1e-10;
 constexpr double LUCKY_TAU_TWO_SIDED = 1e-8;
 constexpr double SERIOUS_TAU = 1e-12;
 constexpr int ELL0 = 16;                   // first inner size of ell-doubling
+constexpr int HOT_BYTES = 96 * 1024;       // LDS for the k-length arrays of the nested step
 
 // ---- scalar helpers for T = double (real) or double2 (complex)
 __device__ inline double s_mul(double a, double b) { return a * b; }
@@ -638,7 +639,38 @@ struct Smem {
     int* redi;        // NT/64
     void* scan;       // NT affine maps
     void* panel;      // GJ_PANEL_BYTES: the Gauss-Jordan panel of RHi
+    void* hot = nullptr;   // HOT_BYTES (null: the nest area stays in global memory)
 };
+
+// Every inner step is a chain of short phases (tridiagonal solves, products,
+// reductions), each reading what the previous one wrote, and the LU is a
+// serial sweep by one thread; from global memory each phase waits on L2
+// latency.  The k-length arrays of the job's own level move to LDS, in this
+// order, as many as fit: LU factors and pivots, solve and work vectors, then
+// H_k itself.  Only the space used within one launch moves (c, the bases and
+// the RHi matrices stay in the nest area), and the arithmetic is unchanged.
+template <typename T>
+__device__ void place_hot(NestPtrs& P, int k, const Smem& sm) {
+    constexpr bool CPLX = sizeof(T) == sizeof(double2);
+    if (!sm.hot) return;
+    char* q = static_cast<char*>(sm.hot);
+    size_t left = HOT_BYTES;
+    const size_t vb = ((size_t)k * sizeof(T) + 15) & ~(size_t)15;
+    const size_t ib = ((size_t)k * sizeof(int) + 15) & ~(size_t)15;
+    auto take = [&](void*& a, size_t n) {
+        if (n > left) return false;
+        a = q;
+        q += n;
+        left -= n;
+        return true;
+    };
+    void* piv = P.piv;
+    if (!take(P.lf, vb) || !take(P.u0, vb) || !take(P.u1, vb) || !take(P.u2, vb) || !take(piv, ib)) return;
+    P.piv = static_cast<int*>(piv);
+    if (!take(P.t, vb) || !take(P.v, vb) || !take(P.r, vb) || !take(P.vp, vb)) return;
+    if (CPLX && (!take(P.w, vb) || !take(P.l, vb) || !take(P.wp, vb))) return;
+    if (!take(P.d, vb) || !take(P.sub, vb) || !take(P.sup, vb)) return;
+}
 
 // ---------------------------------------------------------------- step 3: p
 // Estimated Ritz-value extremes of the tridiagonal in P.d/sub/sup (H_k, or
@@ -1332,6 +1364,7 @@ __device__ void nested_job(const JobDesc& J, int mode, int j, const Smem& sm, fl
     const bool learned = J.k_policy == NKS_POLICY_LEARNED;
     const bool kpol = J.k_policy != NKS_POLICY_FIXED;
     NestPtrs P = nest_ptrs(J.nest, J.k, J.lcap);
+    place_hot<T>(P, J.k, sm);
     const T* cc = (const T*)P.cc;
     const int ell_start = J.ell_policy == NKS_POLICY_LEARNED ? J.status[ST_ELLSTART] : 0;
 
@@ -1442,6 +1475,7 @@ __global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int
     __shared__ int redi[NT / 64];
     __shared__ Aff2<double2> scan_lds[NT];
     __shared__ double2 panel_lds[GJ_PANEL_BYTES / sizeof(double2)];
+    __shared__ double2 hot_lds[HOT_BYTES / sizeof(double2)];
     __shared__ float net_out[2];
     Smem sm;
     sm.red = red;
@@ -1449,6 +1483,7 @@ __global__ __launch_bounds__(NT) void nested_kernel(JobDesc* jobs, int mode, int
     sm.redi = redi;
     sm.scan = scan_lds;
     sm.panel = panel_lds;
+    sm.hot = hot_lds;
     const JobDesc& J = jobs[blockIdx.x];
     if (J.two_sided) nested_job<double2>(J, mode, j, sm, net_out);
     else nested_job<double>(J, mode, j, sm, net_out);
@@ -1496,6 +1531,7 @@ __global__ __launch_bounds__(NT) void label_kernel(JobDesc* jobs) {
     sm.redi = redi;
     sm.scan = scan_lds;
     sm.panel = panel_lds;
+    sm.hot = nullptr;
     const JobDesc& J = jobs[blockIdx.x];
     if (J.two_sided) label_point<double2>(J, blockIdx.y, sm);
     else label_point<double>(J, blockIdx.y, sm);
