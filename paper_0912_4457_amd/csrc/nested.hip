@@ -169,23 +169,39 @@ template <typename T> __device__ inline Aff2<T> compose(const Aff2<T>& l, const 
     return r;
 }
 
+// Lane shuffles of the scalar types and of the affine maps
+__device__ inline double shfl_s(double v, int src) { return __shfl(v, src, 64); }
+__device__ inline double2 shfl_s(double2 v, int src) { return mk(__shfl(v.x, src, 64), __shfl(v.y, src, 64)); }
+template <typename T> __device__ inline Aff1<T> shfl_map(const Aff1<T>& x, int src) {
+    return {shfl_s(x.a, src), shfl_s(x.b, src)};
+}
+template <typename T> __device__ inline Aff2<T> shfl_map(const Aff2<T>& x, int src) {
+    return {shfl_s(x.m00, src), shfl_s(x.m01, src), shfl_s(x.m10, src),
+            shfl_s(x.m11, src), shfl_s(x.g0, src), shfl_s(x.g1, src)};
+}
+
 // Exclusive scan over scan positions 0..NT-1 (position pos composes after
-// positions < pos).  Returns the composition of all maps at positions < pos.
+// positions < pos); pos is tid (rev = false) or NT-1-tid (rev = true).
+// Returns the composition of all maps at positions < pos.  Within a
+// wavefront a Hillis-Steele scan over lane shuffles, then every wavefront
+// composes the totals of the wavefronts before it (two barriers in all).
 template <typename Map>
-__device__ Map block_exclusive_scan(Map x, int pos, Map* lds, Map id) {
-    lds[pos] = x;
-    __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        Map y = x;
-        if (pos >= off) y = compose(x, lds[pos - off]);
-        __syncthreads();
-        lds[pos] = y;
-        x = y;
-        __syncthreads();
+__device__ Map block_exclusive_scan(Map x, bool rev, Map* lds, Map id) {
+    const int lane = threadIdx.x & 63;
+    const int r = rev ? 63 - lane : lane;                           // rank in position order
+    const int wv = rev ? (NT / 64 - 1 - (int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
+    for (int off = 1; off < 64; off <<= 1) {
+        const int src = rev ? min(lane + off, 63) : max(lane - off, 0);
+        const Map y = shfl_map(x, src);
+        if (r >= off) x = compose(x, y);
     }
-    Map ex = (pos > 0) ? lds[pos - 1] : id;
+    if (r == 63) lds[wv] = x;                                        // wavefront total
+    const Map in = shfl_map(x, rev ? min(lane + 1, 63) : max(lane - 1, 0));
     __syncthreads();
-    return ex;
+    Map pre = id;
+    for (int w = 0; w < wv; ++w) pre = compose(lds[w], pre);
+    __syncthreads();
+    return (r == 0) ? pre : compose(in, pre);
 }
 
 struct LUF {   // LU factors of p H_k (gttrf layout) in the nest area
@@ -213,7 +229,7 @@ __device__ void solve_n(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
                                           : Aff1<T>{s_one<T>(), s_scale(s_mul(dl[i], e), -1.0)};
             f = compose(st, f);
         }
-        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, tid, (Aff1<T>*)scan_lds, ident1<T>());
+        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, false, (Aff1<T>*)scan_lds, ident1<T>());
         T c = s_add(s_mul(ex.a, b[0]), ex.b);
         for (int i = i0; i < i1; ++i) {
             const T e = b[i + 1];
@@ -226,7 +242,6 @@ __device__ void solve_n(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
     __syncthreads();
     // backward sweep with U: s_i = (x_i, x_{i+1}) = M_i s_{i+1} + g_i, i = n-2 .. 0
     {
-        const int pos = NT - 1 - tid;   // later rows are composed first
         Aff2<T> f = ident2<T>();
         for (int i = i1 - 1; i >= i0; --i) {
             const T inv = s_div(s_one<T>(), d[i]);
@@ -235,7 +250,7 @@ __device__ void solve_n(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
                        s_one<T>(), s_zero<T>(), s_mul(t[i], inv), s_zero<T>()};
             f = compose(st, f);
         }
-        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, pos, (Aff2<T>*)scan_lds, ident2<T>());
+        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, true, (Aff2<T>*)scan_lds, ident2<T>());
         const T xl = s_div(t[n - 1], d[n - 1]);
         T s0 = s_add(s_mul(ex.m00, xl), ex.g0);
         T s1 = s_add(s_mul(ex.m10, xl), ex.g1);
@@ -273,7 +288,7 @@ __device__ void solve_c(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
                        s_one<T>(), s_zero<T>(), s_mul(b[i], inv), s_zero<T>()};
             f = compose(st, f);
         }
-        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, tid, (Aff2<T>*)scan_lds, ident2<T>());
+        Aff2<T> ex = block_exclusive_scan<Aff2<T>>(f, false, (Aff2<T>*)scan_lds, ident2<T>());
         const T x0 = s_div(b[0], s_conj(d[0]));
         T s0 = s_add(s_mul(ex.m00, x0), ex.g0);
         T s1 = s_add(s_mul(ex.m10, x0), ex.g1);
@@ -290,7 +305,6 @@ __device__ void solve_c(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
     __syncthreads();
     // backward sweep with L^H and the interchanges: carry c, steps i = n-2 .. 0
     {
-        const int pos = NT - 1 - tid;
         const int j0 = tid * m, j1 = min(steps, j0 + m);   // steps j0..j1-1, run descending
         Aff1<T> f = ident1<T>();
         for (int i = j1 - 1; i >= j0; --i) {
@@ -298,7 +312,7 @@ __device__ void solve_c(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
                                           : Aff1<T>{s_one<T>(), s_zero<T>()};
             f = compose(st, f);
         }
-        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, pos, (Aff1<T>*)scan_lds, ident1<T>());
+        Aff1<T> ex = block_exclusive_scan<Aff1<T>>(f, true, (Aff1<T>*)scan_lds, ident1<T>());
         T c = s_add(s_mul(ex.a, t[n - 1]), ex.b);
         for (int i = j1 - 1; i >= j0; --i) {
             if (F.ipiv[i] == i) { x[i + 1] = c; c = s_sub(t[i], s_mul(s_conj(dl[i]), c)); }
