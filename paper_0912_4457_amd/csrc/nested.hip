@@ -529,6 +529,8 @@ __device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ pe
     const int tid = threadIdx.x;
     T* pr = fcol - GJ_NB;                    // scaled pivot row of the panel (kept just before fcol)
     bool ok = true;
+    __shared__ int gj_ok;                    // a zero pivot seen by the single-wavefront panel
+    if (tid == 0) gj_ok = 1;
     for (int i = tid; i < n; i += NT) pinv[i] = -1;
     __syncthreads();
     const int nc = n < NT ? n : NT;
@@ -541,33 +543,90 @@ __device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ pe
             W[e] = sidx < nb ? B[(size_t)i * n + k0 + sidx] : s_zero<T>();
         }
         __syncthreads();
-        // eliminate the panel in LDS
-        for (int t = 0; t < nb; ++t) {
-            double best = -1.0;
-            int bidx = n;
-            for (int i = tid; i < n; i += NT) {
-                const double a = pivot_weight(pinv[i], s_abs(W[i * NB + t]));
-                if (a > best) { best = a; bidx = i; }
-            }
-            const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
-            const T piv = W[p * NB + t];
-            if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
-            const T pivinv = s_div(s_one<T>(), piv);
-            if (tid < NB) pr[tid] = (tid == t) ? pivinv : s_mul(W[p * NB + tid], pivinv);
-            __syncthreads();
-            if (tid == 0) { perm[k0 + t] = p; pinv[p] = k0 + t; }
-            for (int i = tid; i < n; i += NT) {
-                T* w = W + i * NB;
-                if (i == p) {
+        if (n <= 64) {
+            // n <= 64: the first wavefront eliminates the panel alone, one row per
+            // lane held in registers; the pivot search and the pivot row travel
+            // by lane shuffles (same pivots and operations, no barriers; the
+            // complex products may be fused into FMAs differently)
+            if (tid < 64) {
+                const int i = tid;
+                int used = (i < n) ? pinv[i] : 0;
+                T w[NB];
 #pragma unroll
-                    for (int s2 = 0; s2 < NB; ++s2) w[s2] = pr[s2];
-                } else {
-                    const T f = w[t];
+                for (int s2 = 0; s2 < NB; ++s2) w[s2] = (i < n) ? W[i * NB + s2] : s_zero<T>();
 #pragma unroll
-                    for (int s2 = 0; s2 < NB; ++s2) w[s2] = s_sub(s2 == t ? s_zero<T>() : w[s2], s_mul(f, pr[s2]));
+                for (int t = 0; t < NB; ++t) {
+                    if (t >= nb) break;
+                    double best = -1.0;
+                    int bidx = n;
+                    if (i < n) {
+                        const double a = pivot_weight(used, s_abs(w[t]));
+                        if (a > best) { best = a; bidx = i; }
+                    }
+                    for (int m = 32; m >= 1; m >>= 1) {
+                        const double ov = __shfl_xor(best, m, 64);
+                        const int oi = __shfl_xor(bidx, m, 64);
+                        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+                    }
+                    const int p = bidx;   // an unused row exists, so p < n <= 64
+                    T prv[NB];
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) prv[s2] = shfl_s(w[s2], p);
+                    const T piv = prv[t];
+                    if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
+                    const T pivinv = s_div(s_one<T>(), piv);
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) prv[s2] = (s2 == t) ? pivinv : s_mul(prv[s2], pivinv);
+                    if (tid == 0) perm[k0 + t] = p;
+                    if (i < n) {
+                        if (i == p) {
+                            used = k0 + t;
+#pragma unroll
+                            for (int s2 = 0; s2 < NB; ++s2) w[s2] = prv[s2];
+                        } else {
+                            const T f = w[t];
+#pragma unroll
+                            for (int s2 = 0; s2 < NB; ++s2) w[s2] = s_sub(s2 == t ? s_zero<T>() : w[s2], s_mul(f, prv[s2]));
+                        }
+                    }
                 }
+                if (i < n) {
+                    pinv[i] = used;
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) W[i * NB + s2] = w[s2];
+                }
+                if (tid == 0 && !ok) gj_ok = 0;
             }
             __syncthreads();
+        } else {
+            // eliminate the panel in LDS
+            for (int t = 0; t < nb; ++t) {
+                double best = -1.0;
+                int bidx = n;
+                for (int i = tid; i < n; i += NT) {
+                    const double a = pivot_weight(pinv[i], s_abs(W[i * NB + t]));
+                    if (a > best) { best = a; bidx = i; }
+                }
+                const int p = block_argmax(best, bidx, ldsd, ldsi);   // synchronises
+                const T piv = W[p * NB + t];
+                if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
+                const T pivinv = s_div(s_one<T>(), piv);
+                if (tid < NB) pr[tid] = (tid == t) ? pivinv : s_mul(W[p * NB + tid], pivinv);
+                __syncthreads();
+                if (tid == 0) { perm[k0 + t] = p; pinv[p] = k0 + t; }
+                for (int i = tid; i < n; i += NT) {
+                    T* w = W + i * NB;
+                    if (i == p) {
+    #pragma unroll
+                        for (int s2 = 0; s2 < NB; ++s2) w[s2] = pr[s2];
+                    } else {
+                        const T f = w[t];
+    #pragma unroll
+                        for (int s2 = 0; s2 < NB; ++s2) w[s2] = s_sub(s2 == t ? s_zero<T>() : w[s2], s_mul(f, pr[s2]));
+                    }
+                }
+                __syncthreads();
+            }
         }
         // rank-nb update of the columns outside the panel
         if (groups > 1) {
@@ -598,7 +657,7 @@ __device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ pe
         }
         __syncthreads();
     }
-    return ok;
+    return ok && gj_ok != 0;
 }
 
 // The widest panel that fits in GJ_PANEL_BYTES of LDS.
