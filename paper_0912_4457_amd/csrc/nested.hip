@@ -107,31 +107,44 @@ __device__ inline double block_norm2(const T* a, int n, double2* lds) {
 // ---- LAPACK-style tridiagonal LU with partial pivoting (serial, one thread)
 // dl: multipliers (n-1), d: U diagonal (n), du: first super-diagonal (n-1),
 // du2: second super-diagonal (n-2), ipiv: 0-based pivot rows.  Returns info.
+// The running d[i] and du[i] are carried in registers, so no step waits on
+// reading back what the previous one stored.
 template <typename T>
-__device__ int gttrf(int n, T* dl, T* d, T* du, T* du2, int* ipiv) {
+__device__ int gttrf(int n, T* __restrict__ dl, T* __restrict__ d, T* __restrict__ du, T* __restrict__ du2,
+                     int* __restrict__ ipiv) {
     for (int i = 0; i < n; ++i) ipiv[i] = i;
     for (int i = 0; i + 2 < n; ++i) du2[i] = s_zero<T>();
+    T dc = d[0];                                   // d[i] as updated by the steps before i
+    T uc = (n > 1) ? du[0] : s_zero<T>();          // du[i] likewise
     for (int i = 0; i + 1 < n; ++i) {
-        if (s_abs1(d[i]) >= s_abs1(dl[i])) {
-            if (s_abs1(d[i]) != 0.0) {
-                const T fact = s_div(dl[i], d[i]);
+        const T l = dl[i];
+        T dn = d[i + 1];                           // d[i+1] and du[i+1] are still the input values
+        const T un = (i + 2 < n) ? du[i + 1] : s_zero<T>();
+        T un_next = un;
+        if (s_abs1(dc) >= s_abs1(l)) {
+            if (s_abs1(dc) != 0.0) {
+                const T fact = s_div(l, dc);
                 dl[i] = fact;
-                d[i + 1] = s_sub(d[i + 1], s_mul(fact, du[i]));
+                dn = s_sub(dn, s_mul(fact, uc));
             }
-        } else {
-            const T fact = s_div(d[i], dl[i]);
-            d[i] = dl[i];
+            d[i] = dc;
+            du[i] = uc;
+        } else {                                   // interchange rows i and i+1
+            const T fact = s_div(dc, l);
+            d[i] = l;
             dl[i] = fact;
-            const T temp = du[i];
-            du[i] = d[i + 1];
-            d[i + 1] = s_sub(temp, s_mul(fact, d[i + 1]));
+            du[i] = dn;
+            dn = s_sub(uc, s_mul(fact, dn));
             if (i + 2 < n) {
-                du2[i] = du[i + 1];
-                du[i + 1] = s_scale(s_mul(fact, du[i + 1]), -1.0);
+                du2[i] = un;
+                un_next = s_scale(s_mul(fact, un), -1.0);
             }
             ipiv[i] = i + 1;
         }
+        dc = dn;
+        uc = un_next;
     }
+    d[n - 1] = dc;
     for (int i = 0; i < n; ++i)
         if (s_abs1(d[i]) == 0.0) return i + 1;
     return 0;
@@ -1019,12 +1032,15 @@ __device__ void inner_extend(const NestPtrs& P, int k, double p, int m, Inner& s
 }
 
 // ---------------------------------------------------------------- step 5: RHi and c
-// c = V_m sgn(H_m) e_1 for the leading m x m inner Ritz matrix -> out (k)
+// c = V_m sgn(H_m) e_1 for the leading m x m inner Ritz matrix -> out (k).
+// lds_b: the inner space will not grow again, so the LDS of the level's
+// k-length arrays is free and holds the inverted matrix B when it fits.
 template <typename T>
-__device__ int inner_coeffs(const JobDesc& J, const NestPtrs& P, int k, int m, T* out, const Smem& sm) {
+__device__ int inner_coeffs(const JobDesc& J, const NestPtrs& P, int k, int m, T* out, const Smem& sm,
+                            bool lds_b = false) {
     const int tid = threadIdx.x;
     T* S = (T*)P.S;
-    T* B = (T*)P.B;
+    T* B = (lds_b && sm.hot && (size_t)m * m * sizeof(T) <= (size_t)HOT_BYTES) ? (T*)sm.hot : (T*)P.B;
     const T* al = (const T*)P.al;
     const T* bl = (const T*)P.bl;
     const T* gl = (const T*)P.gl;
@@ -1259,7 +1275,7 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     if (!doubling) {
         inner_extend<T>(P, kk, p, min(ell0, cap), in, sm);
         if (J.levels > 1) res.rhi = deep_coeffs<T>(J, P, kk, in.i, cc, sm, res);
-        else res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm);
+        else res.rhi = inner_coeffs<T>(J, P, kk, in.i, cc, sm, true);
         res.ell = in.i;
     } else {
         int ell = min(ell0, cap);

@@ -37,8 +37,11 @@ def test_ell_doubling_matches_oracle(mu, tol):
     c_gpu, st = nks.nested_step(ctx(), kr.alpha, kr.beta, kr.gamma, herm, 400, p=p,
                                 ell_policy=DOUBLING, tol=tol)
     assert st["ell_used"] == (info["ell"] if info["nested"] else 0)
-    assert st["inner_delta"] == pytest.approx(info["inner_delta"], rel=1e-3, abs=1e-14)
-    assert rel(c_gpu, c_ref) <= (1e-11 if herm else 1e-9)
+    # inner_delta = |c_2ell - c_ell| / |c_2ell| is a difference of two coefficient
+    # vectors, each held to ctol of the oracle's below: it can differ by 2 ctol
+    ctol = 1e-11 if herm else 1e-9
+    assert st["inner_delta"] == pytest.approx(info["inner_delta"], rel=1e-3, abs=2 * ctol)
+    assert rel(c_gpu, c_ref) <= ctol
 
 
 @pytest.mark.parametrize("mu", [0.0, 0.3])
