@@ -160,6 +160,9 @@ def run_path(nks, torch, ctx, precision, steps, warmup, gold, profile, tune=True
         from paper_0912_4457_amd.autotune import autotune
         tuned = autotune(ctx, jobs, use_cache=False)
         log(f"[bench] autotune {precision}: {tuned['choice']} {tuned['timings']}")
+        from paper_0912_4457_amd.autotune import schedule
+        tuned["schedule"] = schedule(ctx, jobs)
+        log(f"[bench] schedule {precision}: {tuned['schedule']['choice']} {tuned['schedule']['seconds_per_call']}")
     slots = inflight_slots(nks, torch, jobs, INFLIGHT)
     run_slots(nks, torch, slots, max(warmup, INFLIGHT))
     torch.cuda.synchronize()
@@ -550,7 +553,7 @@ def main():
     log(f"[bench] {other} path for comparison")
     other_run = run_path(nks, torch, ctx, other, max(2, a.steps // 2), 1, gold, profile=False)
     if main_run["tuned"]:                       # the comparison path re-tuned the context
-        for k_, v_ in main_run["tuned"]["choice"].items():
+        for k_, v_ in {**main_run["tuned"]["choice"], **main_run["tuned"]["schedule"]["choice"]}.items():
             ctx.tune_set(k_, v_)
     lats_g, jobs_g = make_jobs(nks, torch, ctx, a.precision)
     graph_dt = time_calls(nks, torch, jobs_g, a.steps, 1, graph=True)

@@ -353,6 +353,12 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  *                its stream; 0 (default): one nested launch for all jobs
  *                after the join (measured 1 % faster at 10^4: the lift of one
  *                group competes with the other group's stencil for HBM)
+ *   "stagger_groups" 0..100 (with pipelined groups): the group with the
+ *                costliest nested step (two-sided first, then the largest k)
+ *                starts first and the others wait until it has done this
+ *                percentage of its outer loop, so that their outer passes
+ *                fill the CUs its nested step leaves idle; 0: all start
+ *                together
  *   "graph"      1: capture and replay batched calls as HIP graphs (see
  *                nks_sign_apply_batch); 0: launch eagerly.
  * Read-only counters: "graph_captures", "graph_replays".

@@ -5,8 +5,12 @@ For a batch of jobs it times every combination of the context's tuning keys
 basis for ``k_probe`` steps, stencil and recurrence passes timed with the
 library's sampled HIP events), keeps the fastest, applies it to the context
 and caches it in a JSON file keyed by (GPU arch, lattice dims, jobs per
-lattice, precision, Hermitian / two-sided).  Every choice gives bit-identical
-results, so tuning never changes a result.
+lattice, precision, Hermitian / two-sided).  ``schedule`` then times whole
+batched calls for the order of the lattice groups (all nested steps after
+all outer loops, or each group's nested step after its own loop with the
+other groups started late, ``stagger_groups`` percent into the lead group's
+loop).  Every choice gives bit-identical results, so tuning never changes a
+result.
 
 Cache file: ``$NKS_TUNE_CACHE`` or ``~/.cache/nks/tune.json``.
 """
@@ -96,3 +100,39 @@ def autotune(ctx, jobs, k_probe: int = 48, use_cache: bool = True) -> dict:
     for k_, v_ in choice.items():
         ctx.tune_set(k_, v_)
     return {"key": key, "choice": choice, "timings": cache.get(key, {}).get("ms_per_iteration")}
+
+
+SCHEDULES = ({"pipeline_groups": 0, "stagger_groups": 0},) + tuple(
+    {"pipeline_groups": 1, "stagger_groups": s} for s in (0, 20, 30, 40, 50))
+
+
+def schedule(ctx, jobs, calls: int = 4, rounds: int = 2) -> dict:
+    """Pick and apply the fastest group schedule for this batch by timing
+    whole calls (graph replay, no stats); returns the choice and the best
+    seconds per call of every candidate."""
+    import time
+    import torch
+    import paper_0912_4457_amd as nks
+    if len({(id(j["lat"]), j.get("precision", "fp64")) for j in jobs}) < 2:
+        choice = dict(SCHEDULES[0])
+        for k_, v_ in choice.items():
+            ctx.tune_set(k_, v_)
+        return {"choice": choice, "seconds_per_call": {}}
+    best = {}
+    for _ in range(rounds):
+        for cfg in SCHEDULES:
+            for k_, v_ in cfg.items():
+                ctx.tune_set(k_, v_)
+            nks.sign_apply_batch(jobs, stats=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(calls):
+                nks.sign_apply_batch(jobs, stats=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / calls
+            key = json.dumps(cfg, sort_keys=True)
+            best[key] = min(best.get(key, dt), dt)
+    choice = json.loads(min(best, key=best.get))
+    for k_, v_ in choice.items():
+        ctx.tune_set(k_, v_)
+    return {"choice": choice, "seconds_per_call": best}

@@ -45,6 +45,7 @@ struct nks_ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> join;
     hipEvent_t fork = nullptr;
+    hipEvent_t lead = nullptr;    // staggered groups: the lead group reached its start point
     struct Graph {
         std::vector<char> key;
         hipGraphExec_t exec = nullptr;
@@ -433,6 +434,7 @@ enum Phase { PH_ALL = 0, PH_OUTER_ONLY = 1, PH_LABEL = 2 };
 // priority).  With concurrency off every group uses the call's stream.
 int ensure_side_streams(nks_ctx* ctx, size_t ngroups) {
     if (!ctx->fork) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    if (!ctx->lead) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->lead, hipEventDisableTiming));
     while (ctx->side.size() + 1 < ngroups) {
         hipStream_t st;
         HIP_TRY(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -474,13 +476,36 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
     // own nested step and lift right after its outer loop, so they overlap the
     // outer loops of slower groups.
     const bool pipe = !timed && phase == PH_ALL && ctx->tune.concurrent && ctx->tune.pipeline && ng >= 2;
+    // Staggered start (pipelined groups): the group with the costliest nested
+    // step (two-sided first, then the largest k) is enqueued first and the
+    // others wait until it has done stagger % of its outer loop, so that their
+    // outer passes still run while its nested step leaves most CUs idle.
+    size_t lead = 0;
+    int lead_j = 0;
+    if (pipe && ctx->tune.stagger > 0) {
+        auto cost = [&](size_t g) {
+            const JobPlan& jp = P.jobs[P.groups[g].first];
+            int kmax = 0;
+            for (int i = P.groups[g].first; i < P.groups[g].first + P.groups[g].second; ++i)
+                kmax = std::max(kmax, P.jobs[i].k);
+            return (jp.two_sided ? 2.0 : 1.0) * kmax;
+        };
+        for (size_t g = 1; g < ng; ++g)
+            if (cost(g) > cost(lead)) lead = g;
+        int kl = 0;
+        for (int i = P.groups[lead].first; i < P.groups[lead].first + P.groups[lead].second; ++i)
+            kl = std::max(kl, P.jobs[i].k);
+        lead_j = std::max(1, kl * ctx->tune.stagger / 100);
+    }
     if (timed) HIP_TRY(ctx, hipEventRecord(ctx->ev[0], s0));
     int frc = fork_groups(ctx, ng, s0);
     if (frc) return frc;
-    for (size_t gi = 0; gi < ng; ++gi) {
+    for (size_t oi = 0; oi < ng; ++oi) {
+        const size_t gi = lead_j ? (oi == 0 ? lead : (oi <= lead ? oi - 1 : oi)) : oi;
         hipStream_t s = group_stream(ctx, gi, ng, s0);
         OuterLaunch L = group_launch(ctx, P, (int)gi, table);
         const int start = P.groups[gi].first;
+        if (lead_j && gi != lead) HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->lead, 0));
         bool kpol = false, learned = false, klearned = false;
         for (int i = start; i < start + L.njobs; ++i) {
             kpol = kpol || P.jobs[i].k_policy != NKS_POLICY_FIXED;
@@ -501,6 +526,7 @@ int enqueue_kernels(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& des
                 if (kpol && (j % CKPT_DK == 0 || (klearned && j > LEARN_K0 && j % LEARN_DK == 0)))
                     launch_checkpoint(L.jobs, L.njobs, j, s);
             }
+            if (lead_j && gi == lead && j == std::min(lead_j, L.kmax)) HIP_TRY(ctx, hipEventRecord(ctx->lead, s));
         }
         if (pipe) {
             launch_finalize(L.jobs, L.njobs, s);
@@ -692,6 +718,7 @@ void nks_destroy(nks_ctx* ctx) {
     for (auto& st : ctx->side) (void)hipStreamDestroy(st);
     for (auto& e : ctx->join) (void)hipEventDestroy(e);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->lead) (void)hipEventDestroy(ctx->lead);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
 }
@@ -1150,6 +1177,10 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
     } else if (k == "split_dual") ctx->tune.split_dual = value != 0;
     else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;
     else if (k == "pipeline_groups") ctx->tune.pipeline = value != 0;
+    else if (k == "stagger_groups") {
+        if (value < 0 || value > 100) return fail(ctx, NKS_E_INVALID, "stagger_groups takes 0..100 (percent)");
+        ctx->tune.stagger = value;
+    }
     else if (k == "min_waves") {
         if (value != 1 && value != 3 && value != 4) return fail(ctx, NKS_E_INVALID, "min_waves takes 1, 3 or 4");
         ctx->tune.min_waves = value;
@@ -1166,6 +1197,7 @@ int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
     else if (k == "min_waves") *value = ctx->tune.min_waves;
     else if (k == "concurrent_groups") *value = ctx->tune.concurrent;
     else if (k == "pipeline_groups") *value = ctx->tune.pipeline;
+    else if (k == "stagger_groups") *value = ctx->tune.stagger;
     else if (k == "graph") *value = ctx->graph;
     else if (k == "graph_captures") *value = (int)ctx->graph_captures;
     else if (k == "graph_replays") *value = (int)ctx->graph_replays;

@@ -245,6 +245,7 @@ struct Tuning {
     int min_waves = 1;    // stencil kernels: register budget for 1 (unlimited), 3 or 4 waves per SIMD
     int concurrent = 1;   // lattice groups of a batch on separate streams (1) or one after another (0)
     int pipeline = 0;     // with concurrent groups: each group's nested step and lift follow its own outer loop
+    int stagger = 0;      // pipelined groups: the others start once the lead group has done this % of its loop
 };
 
 // Start/stop events of a timed launch (nks_profile_enable), stamped by the

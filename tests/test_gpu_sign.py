@@ -143,6 +143,62 @@ def test_tuning_choices_are_bitwise_identical():
         c.tune_set("concurrent_groups", 1)
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_staggered_group_schedules_are_bitwise_identical(graph):
+    # pipelined and staggered group orders (the lead is the two-sided group)
+    # give the same bits as all nested steps after all loops, eager and replayed
+    import paper_0912_4457_amd as nks
+    from gpu_common import ctx
+    c = ctx()
+    la = lattice((4, 4, 4, 6), 0.5, 21, 0.0)
+    lb = lattice((4, 4, 4, 6), 0.5, 21, 0.25)
+    jobs = [dict(lat=la, b=I.gaussian_source((4, 4, 4, 6), 5).ravel(), k=80, ell=20),
+            dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=80, ell=20),
+            dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20),
+            dict(lat=la, b=I.point_source((4, 4, 4, 6), 2, 1).ravel(), k=200, ell=30, tol=1e-8,
+                 k_policy=nks.POLICY_DOUBLING)]
+    ref = None
+    c.tune_set("graph", graph)
+    try:
+        for pipe, st in ((0, 0), (1, 0), (1, 1), (1, 30), (1, 100), (0, 50)):
+            c.tune_set("pipeline_groups", pipe)
+            c.tune_set("stagger_groups", st)
+            for _ in range(2):
+                xs, _ = nks.sign_apply_batch(jobs, stats=False)
+                got = [to_np(x) for x in xs]
+                if ref is None:
+                    ref = got
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b)
+    finally:
+        c.tune_set("graph", 1)
+        c.tune_set("pipeline_groups", 0)
+        c.tune_set("stagger_groups", 0)
+    with pytest.raises(nks.NKSError):
+        c.tune_set("stagger_groups", 101)
+
+
+def test_schedule_autotuner_applies_a_choice():
+    import paper_0912_4457_amd as nks
+    from paper_0912_4457_amd import autotune
+    from gpu_common import ctx
+    c = ctx()
+    la = lattice((4, 4, 4, 6), 0.5, 21, 0.0)
+    lb = lattice((4, 4, 4, 6), 0.5, 21, 0.25)
+    jobs = [dict(lat=la, b=I.gaussian_source((4, 4, 4, 6), 5).ravel(), k=60, ell=16),
+            dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=60, ell=16)]
+    try:
+        res = autotune.schedule(c, jobs, calls=1, rounds=1)
+        assert len(res["seconds_per_call"]) == len(autotune.SCHEDULES)
+        assert c.tune_get("pipeline_groups") == res["choice"]["pipeline_groups"]
+        assert c.tune_get("stagger_groups") == res["choice"]["stagger_groups"]
+        one = autotune.schedule(c, jobs[:1])          # one group: nothing to schedule
+        assert one["choice"] == {"pipeline_groups": 0, "stagger_groups": 0}
+    finally:
+        c.tune_set("pipeline_groups", 0)
+        c.tune_set("stagger_groups", 0)
+
+
 def test_autotuner_picks_and_applies_a_choice(tmp_path, monkeypatch):
     import paper_0912_4457_amd as nks
     from paper_0912_4457_amd import autotune
