@@ -414,21 +414,54 @@ __device__ inline int sturm_count(const double* d, const double* sub, int k, dou
     return cnt;
 }
 
-// m-th smallest eigenvalue (1-based) by 256-way multisection of [-G, G]
-__device__ double find_eig(const double* d, const double* sub, int k, int m, double G, double pivmin,
-                           double* ldsd) {
-    double lo = -G, hi = G;
-    for (int round = 0; round < 4; ++round) {
-        const double x = lo + (hi - lo) * (double)(threadIdx.x + 1) / (double)(NT + 1);
-        const int c = sturm_count(d, sub, k, x, pivmin);
-        const double cand_lo = (c < m) ? x : -INFINITY;
-        const double cand_hi = (c >= m) ? x : INFINITY;
-        const double nlo = block_max(cand_lo, ldsd);
-        const double nhi = block_min(cand_hi, ldsd);
-        if (nlo > lo) lo = nlo;
-        if (nhi < hi) hi = nhi;
+// Eigenvalues number ms[0..nt) (1-based, nt <= 8) of the symmetric
+// tridiagonal by multisection of [-G, G]: one NT-point round shared by all
+// targets, then the threads split into nt groups, each refining its own
+// target's bracket, for as many rounds as bring every bracket below the
+// resolution of four NT-point rounds, 2G / (NT+1)^4.  A bracket keeps the
+// largest point with fewer than m eigenvalues below it and the smallest with
+// at least m.  lds: NT ints and 16 doubles.  All threads; results in out.
+__device__ void find_eigs(const double* d, const double* sub, int k, const int* ms, int nt, double G,
+                          double pivmin, void* lds, double* out) {
+    int* cnt = static_cast<int*>(lds);
+    double* lo = reinterpret_cast<double*>(cnt + NT);
+    double* hi = lo + 8;
+    const int tid = threadIdx.x;
+    cnt[tid] = sturm_count(d, sub, k, -G + 2.0 * G * (double)(tid + 1) / (double)(NT + 1), pivmin);
+    __syncthreads();
+    if (tid < nt) {
+        double l = -G, h = G;
+        for (int t = 0; t < NT; ++t) {
+            const double xt = -G + 2.0 * G * (double)(t + 1) / (double)(NT + 1);
+            if (cnt[t] < ms[tid]) l = fmax(l, xt);
+            else h = fmin(h, xt);
+        }
+        lo[tid] = l;
+        hi[tid] = h;
     }
-    return 0.5 * (lo + hi);
+    __syncthreads();
+    const int per = NT / nt;
+    int rounds = 0;
+    for (double f = 1.0; f < (double)(NT + 1) * (NT + 1) * (NT + 1); f *= (double)(per + 1)) ++rounds;
+    const int g = tid / per, j = tid - (tid / per) * per;
+    for (int r = 0; r < rounds; ++r) {
+        if (g < nt) cnt[tid] = sturm_count(d, sub, k, lo[g] + (hi[g] - lo[g]) * (double)(j + 1) / (double)(per + 1), pivmin);
+        __syncthreads();
+        if (tid < nt) {
+            const double ol = lo[tid], oh = hi[tid];
+            double l = ol, h = oh;
+            for (int t = 0; t < per; ++t) {
+                const double xt = ol + (oh - ol) * (double)(t + 1) / (double)(per + 1);
+                if (cnt[tid * per + t] < ms[tid]) l = fmax(l, xt);
+                else h = fmin(h, xt);
+            }
+            lo[tid] = l;
+            hi[tid] = h;
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < nt; ++i) out[i] = 0.5 * (lo[i] + hi[i]);
+    __syncthreads();
 }
 
 // Pivot search key: rows already used never win; every unused row is a
@@ -787,8 +820,25 @@ __device__ void estimate_extremes(const NestPtrs& P, int k, const Smem& sm, doub
         __syncthreads();
         const int c0 = c0s;
         __syncthreads();
-        const double l1 = find_eig(dd, ee, k, 1, G, pivmin, sm.redd);
-        const double lk = find_eig(dd, ee, k, k, G, pivmin, sm.redd);
+        // the extremes and the Ritz values next to the origin (indices c0 - 1 .. c0 + 2)
+        int ms[6], nt = 0;
+        auto add = [&](int m) {
+            if (m < 1 || m > k) return;
+            for (int i = 0; i < nt; ++i)
+                if (ms[i] == m) return;
+            ms[nt++] = m;
+        };
+        add(1);
+        add(k);
+        for (int m = c0 - 1; m <= c0 + 2; ++m) add(m);
+        double ev[6];
+        find_eigs(dd, ee, k, ms, nt, G, pivmin, sm.scan, ev);
+        auto eig = [&](int m) {
+            for (int i = 0; i < nt; ++i)
+                if (ms[i] == m) return ev[i];
+            return 0.0;
+        };
+        const double l1 = eig(1), lk = eig(k);
         zmax = fmax(fabs(l1), fabs(lk));
         if (k == 1) { zmin = fabs(l1); return; }
         // z_min: the second smallest |theta|.  Between two Ritz values lies an
@@ -799,7 +849,7 @@ __device__ void estimate_extremes(const NestPtrs& P, int k, const Smem& sm, doub
         double z1 = INFINITY, z2 = INFINITY;
         for (int m = c0 - 1; m <= c0 + 2; ++m) {
             if (m < 1 || m > k) continue;
-            const double a = fabs(m == 1 ? l1 : (m == k ? lk : find_eig(dd, ee, k, m, G, pivmin, sm.redd)));
+            const double a = fabs(eig(m));
             if (a < z1) { z2 = z1; z1 = a; }
             else if (a < z2) z2 = a;
         }
