@@ -103,7 +103,7 @@ def autotune(ctx, jobs, k_probe: int = 48, use_cache: bool = True) -> dict:
 
 
 SCHEDULES = ({"pipeline_groups": 0, "stagger_groups": 0},) + tuple(
-    {"pipeline_groups": 1, "stagger_groups": s} for s in (0, 20, 30, 40, 50))
+    {"pipeline_groups": 1, "stagger_groups": s} for s in (0, 20, 30, 35, 40, 45, 50))
 
 
 def schedule(ctx, jobs, calls: int = 4, rounds: int = 2) -> dict:
