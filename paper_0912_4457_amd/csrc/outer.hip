@@ -192,7 +192,7 @@ __global__ __launch_bounds__(NT, MINW) void herm_S(JobDesc* jobs, Geom g, const 
         hop_coefs<R>(kappa, 0.0, cf[0], cb[0]);
         const cx_t<R>* const fields[1] = {uj};
         cx_t<R> acc[1][12];
-        wilson_site<R, 1>(g, links, fields, cf, cb, site, acc);
+        wilson_site<R, 1, true>(g, links, fields, cf, cb, site, acc);
         const cx_t<R>* up = (j >= 2) ? column<R>(J, j - 1, n) : nullptr;
         cx_t<R>* rout = (j < J.k) ? column<R>(J, j + 1, n) : nullptr;
 #pragma unroll
