@@ -156,7 +156,9 @@ def test_staggered_group_schedules_are_bitwise_identical(graph):
             dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 6).ravel(), k=80, ell=20),
             dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20),
             dict(lat=la, b=I.point_source((4, 4, 4, 6), 2, 1).ravel(), k=200, ell=30, tol=1e-8,
-                 k_policy=nks.POLICY_DOUBLING)]
+                 k_policy=nks.POLICY_DOUBLING),
+            # a third group (two-sided, mixed precision, the largest k): the lead, enqueued first
+            dict(lat=lb, b=I.gaussian_source((4, 4, 4, 6), 7).ravel(), k=120, ell=20, precision="mixed")]
     ref = None
     c.tune_set("graph", graph)
     try:
