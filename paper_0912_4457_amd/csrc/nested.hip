@@ -337,13 +337,187 @@ __device__ void solve_c(const LUF& F, int n, const T* b, T* t, T* x, void* scan_
     __syncthreads();
 }
 
+// ---- two independent solves in one pass: their scans share the shuffle
+// rounds and barriers; each component keeps the association of its own solve,
+// so the results are those of two separate calls
+template <typename A, typename B> struct MPair { A a; B b; };
+template <typename A, typename B>
+__device__ inline MPair<A, B> compose(const MPair<A, B>& l, const MPair<A, B>& e) {
+    return {compose(l.a, e.a), compose(l.b, e.b)};
+}
+template <typename A, typename B> __device__ inline MPair<A, B> shfl_map(const MPair<A, B>& x, int src) {
+    return {shfl_map(x.a, src), shfl_map(x.b, src)};
+}
+
+// x1 = (L U)^{-1} P b1 and x2 = (L U)^{-1} P b2 (trans 'N' twice); t1 != t2; all threads
+template <typename T>
+__device__ void solve_nn(const LUF& F, int n, const T* b1, T* t1, T* x1, const T* b2, T* t2, T* x2,
+                         void* scan_lds) {
+    const T* dl = (const T*)F.dl;
+    const T* d = (const T*)F.d;
+    const T* du = (const T*)F.du;
+    const T* du2 = (const T*)F.du2;
+    const int tid = threadIdx.x;
+    const int steps = n - 1;
+    const int m = (steps + NT - 1) / NT;
+    const int i0 = tid * m, i1 = min(steps, i0 + m);
+    {
+        MPair<Aff1<T>, Aff1<T>> f{ident1<T>(), ident1<T>()};
+        for (int i = i0; i < i1; ++i) {
+            const bool keep = F.ipiv[i] == i;
+            const T e1 = b1[i + 1], e2 = b2[i + 1];
+            const Aff1<T> s1 = keep ? Aff1<T>{s_scale(dl[i], -1.0), e1} : Aff1<T>{s_one<T>(), s_scale(s_mul(dl[i], e1), -1.0)};
+            const Aff1<T> s2 = keep ? Aff1<T>{s_scale(dl[i], -1.0), e2} : Aff1<T>{s_one<T>(), s_scale(s_mul(dl[i], e2), -1.0)};
+            f.a = compose(s1, f.a);
+            f.b = compose(s2, f.b);
+        }
+        const MPair<Aff1<T>, Aff1<T>> ex = block_exclusive_scan<MPair<Aff1<T>, Aff1<T>>>(
+            f, false, (MPair<Aff1<T>, Aff1<T>>*)scan_lds, {ident1<T>(), ident1<T>()});
+        T c1 = s_add(s_mul(ex.a.a, b1[0]), ex.a.b);
+        T c2 = s_add(s_mul(ex.b.a, b2[0]), ex.b.b);
+        for (int i = i0; i < i1; ++i) {
+            const T e1 = b1[i + 1], e2 = b2[i + 1];
+            if (F.ipiv[i] == i) {
+                t1[i] = c1; c1 = s_sub(e1, s_mul(dl[i], c1));
+                t2[i] = c2; c2 = s_sub(e2, s_mul(dl[i], c2));
+            } else {
+                t1[i] = e1; c1 = s_sub(c1, s_mul(dl[i], e1));
+                t2[i] = e2; c2 = s_sub(c2, s_mul(dl[i], e2));
+            }
+        }
+        if (steps == 0 && tid == 0) { t1[0] = b1[0]; t2[0] = b2[0]; }
+        else if (i1 == steps && i0 < i1) { t1[steps] = c1; t2[steps] = c2; }
+    }
+    __syncthreads();
+    {
+        MPair<Aff2<T>, Aff2<T>> f{ident2<T>(), ident2<T>()};
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            const T a0 = s_scale(s_mul(du[i], inv), -1.0);
+            const T a1 = (i + 2 < n) ? s_scale(s_mul(du2[i], inv), -1.0) : s_zero<T>();
+            const Aff2<T> s1{a0, a1, s_one<T>(), s_zero<T>(), s_mul(t1[i], inv), s_zero<T>()};
+            const Aff2<T> s2{a0, a1, s_one<T>(), s_zero<T>(), s_mul(t2[i], inv), s_zero<T>()};
+            f.a = compose(s1, f.a);
+            f.b = compose(s2, f.b);
+        }
+        const MPair<Aff2<T>, Aff2<T>> ex = block_exclusive_scan<MPair<Aff2<T>, Aff2<T>>>(
+            f, true, (MPair<Aff2<T>, Aff2<T>>*)scan_lds, {ident2<T>(), ident2<T>()});
+        const T xl1 = s_div(t1[n - 1], d[n - 1]), xl2 = s_div(t2[n - 1], d[n - 1]);
+        T p0 = s_add(s_mul(ex.a.m00, xl1), ex.a.g0), p1 = s_add(s_mul(ex.a.m10, xl1), ex.a.g1);
+        T q0 = s_add(s_mul(ex.b.m00, xl2), ex.b.g0), q1 = s_add(s_mul(ex.b.m10, xl2), ex.b.g1);
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            const T dd2 = (i + 2 < n) ? du2[i] : s_zero<T>();
+            const T y1 = s_mul(s_sub(s_sub(t1[i], s_mul(du[i], p0)), s_mul(dd2, p1)), inv);
+            const T y2 = s_mul(s_sub(s_sub(t2[i], s_mul(du[i], q0)), s_mul(dd2, q1)), inv);
+            p1 = p0; p0 = y1; x1[i] = y1;
+            q1 = q0; q0 = y2; x2[i] = y2;
+        }
+        if (tid == 0) { x1[n - 1] = xl1; x2[n - 1] = xl2; }
+    }
+    __syncthreads();
+}
+
+// xn = (L U)^{-1} P bn (trans 'N') and xc = ((L U)^H)^{-1} bc (trans 'C'); tn != tc; all threads
+template <typename T>
+__device__ void solve_nc(const LUF& F, int n, const T* bn, T* tn, T* xn, const T* bc, T* tc, T* xc,
+                         void* scan_lds) {
+    const T* dl = (const T*)F.dl;
+    const T* d = (const T*)F.d;
+    const T* du = (const T*)F.du;
+    const T* du2 = (const T*)F.du2;
+    const int tid = threadIdx.x;
+    const int steps = n - 1;
+    const int m = (steps + NT - 1) / NT;
+    const int i0 = tid * m, i1 = min(steps, i0 + m);           // 'N' steps; 'C' backward steps too
+    const int c0 = 1 + tid * m, c1 = min(n, c0 + m);            // 'C' forward rows
+    // forward: L with interchanges ('N'), U^H ('C')
+    {
+        MPair<Aff1<T>, Aff2<T>> f{ident1<T>(), ident2<T>()};
+        for (int i = i0; i < i1; ++i) {
+            const T e = bn[i + 1];
+            const Aff1<T> st = (F.ipiv[i] == i) ? Aff1<T>{s_scale(dl[i], -1.0), e}
+                                                : Aff1<T>{s_one<T>(), s_scale(s_mul(dl[i], e), -1.0)};
+            f.a = compose(st, f.a);
+        }
+        for (int i = c0; i < c1; ++i) {
+            const T inv = s_div(s_one<T>(), s_conj(d[i]));
+            const Aff2<T> st{s_scale(s_mul(s_conj(du[i - 1]), inv), -1.0),
+                             (i >= 2) ? s_scale(s_mul(s_conj(du2[i - 2]), inv), -1.0) : s_zero<T>(),
+                             s_one<T>(), s_zero<T>(), s_mul(bc[i], inv), s_zero<T>()};
+            f.b = compose(st, f.b);
+        }
+        const MPair<Aff1<T>, Aff2<T>> ex = block_exclusive_scan<MPair<Aff1<T>, Aff2<T>>>(
+            f, false, (MPair<Aff1<T>, Aff2<T>>*)scan_lds, {ident1<T>(), ident2<T>()});
+        T c = s_add(s_mul(ex.a.a, bn[0]), ex.a.b);
+        for (int i = i0; i < i1; ++i) {
+            const T e = bn[i + 1];
+            if (F.ipiv[i] == i) { tn[i] = c; c = s_sub(e, s_mul(dl[i], c)); }
+            else { tn[i] = e; c = s_sub(c, s_mul(dl[i], e)); }
+        }
+        if (steps == 0 && tid == 0) tn[0] = bn[0];
+        else if (i1 == steps && i0 < i1) tn[steps] = c;
+        const T x0 = s_div(bc[0], s_conj(d[0]));
+        T s0 = s_add(s_mul(ex.b.m00, x0), ex.b.g0);
+        T s1 = s_add(s_mul(ex.b.m10, x0), ex.b.g1);
+        for (int i = c0; i < c1; ++i) {
+            const T inv = s_div(s_one<T>(), s_conj(d[i]));
+            const T cc2 = (i >= 2) ? s_conj(du2[i - 2]) : s_zero<T>();
+            const T xi = s_mul(s_sub(s_sub(bc[i], s_mul(s_conj(du[i - 1]), s0)), s_mul(cc2, s1)), inv);
+            s1 = s0;
+            s0 = xi;
+            tc[i] = xi;
+        }
+        if (tid == 0) tc[0] = x0;
+    }
+    __syncthreads();
+    // backward: U ('N'), L^H with interchanges ('C')
+    {
+        MPair<Aff2<T>, Aff1<T>> f{ident2<T>(), ident1<T>()};
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            const Aff2<T> st{s_scale(s_mul(du[i], inv), -1.0),
+                             (i + 2 < n) ? s_scale(s_mul(du2[i], inv), -1.0) : s_zero<T>(),
+                             s_one<T>(), s_zero<T>(), s_mul(tn[i], inv), s_zero<T>()};
+            f.a = compose(st, f.a);
+        }
+        for (int i = i1 - 1; i >= i0; --i) {
+            const Aff1<T> st = (F.ipiv[i] == i) ? Aff1<T>{s_scale(s_conj(dl[i]), -1.0), tc[i]}
+                                                : Aff1<T>{s_one<T>(), s_zero<T>()};
+            f.b = compose(st, f.b);
+        }
+        const MPair<Aff2<T>, Aff1<T>> ex = block_exclusive_scan<MPair<Aff2<T>, Aff1<T>>>(
+            f, true, (MPair<Aff2<T>, Aff1<T>>*)scan_lds, {ident2<T>(), ident1<T>()});
+        const T xl = s_div(tn[n - 1], d[n - 1]);
+        T s0 = s_add(s_mul(ex.a.m00, xl), ex.a.g0);
+        T s1 = s_add(s_mul(ex.a.m10, xl), ex.a.g1);
+        for (int i = i1 - 1; i >= i0; --i) {
+            const T inv = s_div(s_one<T>(), d[i]);
+            const T dd2 = (i + 2 < n) ? du2[i] : s_zero<T>();
+            const T xi = s_mul(s_sub(s_sub(tn[i], s_mul(du[i], s0)), s_mul(dd2, s1)), inv);
+            s1 = s0;
+            s0 = xi;
+            xn[i] = xi;
+        }
+        if (tid == 0) xn[n - 1] = xl;
+        T c = s_add(s_mul(ex.b.a, tc[n - 1]), ex.b.b);
+        for (int i = i1 - 1; i >= i0; --i) {
+            if (F.ipiv[i] == i) { xc[i + 1] = c; c = s_sub(tc[i], s_mul(s_conj(dl[i]), c)); }
+            else { xc[i + 1] = s_sub(tc[i], s_mul(s_conj(dl[i]), c)); }
+        }
+        if (steps == 0) { if (tid == 0) xc[0] = tc[0]; }
+        else if (i0 == 0 && i0 < i1) xc[0] = c;
+    }
+    __syncthreads();
+}
+
 // ---- nest-area layout
 struct NestPtrs {
     void *d, *sub, *sup;        // H_k diagonals (k)
     void *lf, *u0, *u1, *u2;    // LU factors (k each)
     int* piv;                   // k
     void* vl;                   // inner basis, L columns of k
-    void *v, *vp, *w, *wp, *r, *l, *y, *t;   // work vectors (k)
+    void *v, *vp, *w, *wp, *r, *l, *y, *t, *t2;   // work vectors (k)
     void *cc, *cp;              // current and previous coefficient vectors (k)
     void *al, *bl, *gl;         // H_ell (L)
     void *S, *B;                // dense L x L
@@ -353,7 +527,7 @@ struct NestPtrs {
 
 __host__ __device__ inline size_t nest_words_impl(int k, int L) {
     // complex words (16 bytes); int arrays rounded up
-    return (size_t)3 * k + 4 * (size_t)k + ((size_t)k + 3) / 4 + (size_t)k * L + 10 * (size_t)k + 3 * (size_t)L +
+    return (size_t)3 * k + 4 * (size_t)k + ((size_t)k + 3) / 4 + (size_t)k * L + 11 * (size_t)k + 3 * (size_t)L +
            2 * (size_t)L * L + 2 * (size_t)L + ((size_t)L + 3) / 4 + 8;
 }
 
@@ -366,7 +540,7 @@ __device__ inline NestPtrs nest_ptrs(double2* base, int k, int L) {
     P.piv = (int*)take(((size_t)k + 3) / 4);
     P.vl = take((size_t)k * L);
     P.v = take(k); P.vp = take(k); P.w = take(k); P.wp = take(k); P.r = take(k); P.l = take(k); P.y = take(k);
-    P.t = take(k); P.cc = take(k); P.cp = take(k);
+    P.t = take(k); P.t2 = take(k); P.cc = take(k); P.cp = take(k);
     P.al = take(L); P.bl = take(L); P.gl = take(L);
     P.S = take((size_t)L * L); P.B = take((size_t)L * L);
     P.prow = take(L); P.fcol = take(L);
@@ -395,6 +569,28 @@ __device__ void apply_hprime(const NestPtrs& P, int k, double p, const T* v, T* 
             if (i + 1 < k) hv = s_add(hv, s_mul(s_conj(sub[i]), v[i + 1]));
         }
         y[i] = s_scale(s_add(y[i], s_scale(hv, p)), 0.5);
+    }
+    __syncthreads();
+}
+
+// yv = H_k' v and yw = H_k'^dagger w with both solves in one pass (two-sided step)
+template <typename T>
+__device__ void apply_hprime2(const NestPtrs& P, int k, double p, const T* v, T* yv, const T* w, T* yw,
+                              void* scan_lds) {
+    const T* d = (const T*)P.d;
+    const T* sub = (const T*)P.sub;
+    const T* sup = (const T*)P.sup;
+    const LUF F{P.lf, P.u0, P.u1, P.u2, P.piv};
+    solve_nc<T>(F, k, v, (T*)P.t, yv, w, (T*)P.t2, yw, scan_lds);
+    for (int i = threadIdx.x; i < k; i += NT) {
+        T hv = s_mul(d[i], v[i]);
+        if (i > 0) hv = s_add(hv, s_mul(sub[i - 1], v[i - 1]));
+        if (i + 1 < k) hv = s_add(hv, s_mul(sup[i], v[i + 1]));
+        yv[i] = s_scale(s_add(yv[i], s_scale(hv, p)), 0.5);
+        T hw = s_mul(s_conj(d[i]), w[i]);
+        if (i > 0) hw = s_add(hw, s_mul(s_conj(sup[i - 1]), w[i - 1]));
+        if (i + 1 < k) hw = s_add(hw, s_mul(s_conj(sub[i]), w[i + 1]));
+        yw[i] = s_scale(s_add(yw[i], s_scale(hw, p)), 0.5);
     }
     __syncthreads();
 }
@@ -786,7 +982,7 @@ __device__ void place_hot(NestPtrs& P, int k, const Smem& sm) {
     void* piv = P.piv;
     if (!take(P.lf, vb) || !take(P.u0, vb) || !take(P.u1, vb) || !take(P.u2, vb) || !take(piv, ib)) return;
     P.piv = static_cast<int*>(piv);
-    if (!take(P.t, vb) || !take(P.v, vb) || !take(P.r, vb) || !take(P.vp, vb)) return;
+    if (!take(P.t, vb) || !take(P.t2, vb) || !take(P.v, vb) || !take(P.r, vb) || !take(P.vp, vb)) return;
     if (CPLX && (!take(P.w, vb) || !take(P.l, vb) || !take(P.wp, vb))) return;
     if (!take(P.d, vb) || !take(P.sub, vb) || !take(P.sup, vb)) return;
 }
@@ -921,8 +1117,7 @@ __device__ void estimate_extremes(const NestPtrs& P, int k, const Smem& sm, doub
         }
         lsum = 0.0;
         for (int it = 0; it < NIT; ++it) {
-            solve_n<T>(F, k, x, (T*)P.t, y, sm.scan);
-            solve_n<T>(F, k, x2, (T*)P.t, y2, sm.scan);
+            solve_nn<T>(F, k, x, (T*)P.t, y, x2, (T*)P.t2, y2, sm.scan);
             const double n1 = sqrt(block_norm2<T>(y, k, sm.red));
             for (int i = tid; i < k; i += NT) y[i] = s_scale(y[i], 1.0 / n1);
             __syncthreads();
@@ -989,8 +1184,8 @@ __device__ void inner_init(const NestPtrs& P, int k, double p, Inner& st, const 
         if (CPLX) { w[i] = v[i]; wp[i] = s_zero<T>(); }
     }
     __syncthreads();
-    apply_hprime<T, false>(P, k, p, v, (T*)P.r, sm.scan);
-    if (CPLX) apply_hprime<T, true>(P, k, p, w, (T*)P.l, sm.scan);
+    if (CPLX) apply_hprime2<T>(P, k, p, v, (T*)P.r, w, (T*)P.l, sm.scan);
+    else apply_hprime<T, false>(P, k, p, v, (T*)P.r, sm.scan);
     st = Inner{};
 }
 
@@ -1051,8 +1246,7 @@ __device__ void inner_extend(const NestPtrs& P, int k, double p, int m, Inner& s
                 st.vn = nr / cabs(beta);
                 st.wn = nl / cabs(gamma);
                 __syncthreads();
-                apply_hprime<T, false>(P, k, p, v, r, sm.scan);
-                apply_hprime<T, true>(P, k, p, w, l, sm.scan);
+                apply_hprime2<T>(P, k, p, v, r, w, l, sm.scan);
                 for (int q = tid; q < k; q += NT) {
                     r[q] = s_sub(r[q], s_mul(s_from<T>(gamma), vp[q]));
                     l[q] = s_sub(l[q], s_mul(s_from<T>(cconj(beta)), wp[q]));
