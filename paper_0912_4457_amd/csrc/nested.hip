@@ -1278,13 +1278,17 @@ __device__ void inner_extend(const NestPtrs& P, int k, double p, int m, Inner& s
 // ---------------------------------------------------------------- step 5: RHi and c
 // c = V_m sgn(H_m) e_1 for the leading m x m inner Ritz matrix -> out (k).
 // lds_b: the inner space will not grow again, so the LDS of the level's
-// k-length arrays is free and holds the inverted matrix B when it fits.
+// k-length arrays is free and holds the inverted matrix B, and S as well,
+// when they fit.
 template <typename T>
 __device__ int inner_coeffs(const JobDesc& J, const NestPtrs& P, int k, int m, T* out, const Smem& sm,
                             bool lds_b = false) {
     const int tid = threadIdx.x;
-    T* S = (T*)P.S;
-    T* B = (lds_b && sm.hot && (size_t)m * m * sizeof(T) <= (size_t)HOT_BYTES) ? (T*)sm.hot : (T*)P.B;
+    const size_t mm = (size_t)m * m;
+    const bool b_lds = lds_b && sm.hot && mm * sizeof(T) <= (size_t)HOT_BYTES;
+    const bool s_lds = b_lds && 2 * mm * sizeof(T) <= (size_t)HOT_BYTES;
+    T* B = b_lds ? (T*)sm.hot : (T*)P.B;
+    T* S = s_lds ? (T*)sm.hot + mm : (T*)P.S;
     const T* al = (const T*)P.al;
     const T* bl = (const T*)P.bl;
     const T* gl = (const T*)P.gl;
