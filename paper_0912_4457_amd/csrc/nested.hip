@@ -840,6 +840,67 @@ __device__ bool gj_invert_blocked(T* __restrict__ B, int n, int* __restrict__ pe
                 if (tid == 0 && !ok) gj_ok = 0;
             }
             __syncthreads();
+        } else if (n <= NT) {
+            // 64 < n <= NT: one row per thread, held in registers; per pivot the
+            // wavefront maxima meet in LDS (the tie rule of block_argmax) and the
+            // pivot row's owner publishes it: two barriers per pivot
+            const int i = tid;
+            int used = (i < n) ? pinv[i] : 0;
+            T w[NB];
+#pragma unroll
+            for (int s2 = 0; s2 < NB; ++s2) w[s2] = (i < n) ? W[i * NB + s2] : s_zero<T>();
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                if (t >= nb) break;
+                double best = -1.0;
+                int bidx = n;
+                if (i < n) {
+                    const double a = pivot_weight(used, s_abs(w[t]));
+                    if (a > best) { best = a; bidx = i; }
+                }
+                for (int m = 32; m >= 1; m >>= 1) {
+                    const double ov = __shfl_xor(best, m, 64);
+                    const int oi = __shfl_xor(bidx, m, 64);
+                    if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+                }
+                if ((tid & 63) == 0) { ldsd[tid >> 6] = best; ldsi[tid >> 6] = bidx; }
+                __syncthreads();
+                double bv = ldsd[0];
+                int p = ldsi[0];
+                for (int q = 1; q < NT / 64; ++q)
+                    if (ldsd[q] > bv || (ldsd[q] == bv && ldsi[q] < p)) { bv = ldsd[q]; p = ldsi[q]; }
+                if (i == p) {
+#pragma unroll
+                    for (int s2 = 0; s2 < NB; ++s2) pr[s2] = w[s2];
+                }
+                __syncthreads();
+                T prv[NB];
+#pragma unroll
+                for (int s2 = 0; s2 < NB; ++s2) prv[s2] = pr[s2];
+                const T piv = prv[t];
+                if (!(s_abs1(piv) > 0.0) || !isfinite(s_abs1(piv))) ok = false;
+                const T pivinv = s_div(s_one<T>(), piv);
+#pragma unroll
+                for (int s2 = 0; s2 < NB; ++s2) prv[s2] = (s2 == t) ? pivinv : s_mul(prv[s2], pivinv);
+                if (tid == 0) perm[k0 + t] = p;
+                if (i < n) {
+                    if (i == p) {
+                        used = k0 + t;
+#pragma unroll
+                        for (int s2 = 0; s2 < NB; ++s2) w[s2] = prv[s2];
+                    } else {
+                        const T f = w[t];
+#pragma unroll
+                        for (int s2 = 0; s2 < NB; ++s2) w[s2] = s_sub(s2 == t ? s_zero<T>() : w[s2], s_mul(f, prv[s2]));
+                    }
+                }
+            }
+            if (i < n) {
+                pinv[i] = used;
+#pragma unroll
+                for (int s2 = 0; s2 < NB; ++s2) W[i * NB + s2] = w[s2];
+            }
+            __syncthreads();
         } else {
             // eliminate the panel in LDS
             for (int t = 0; t < nb; ++t) {
