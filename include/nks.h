@@ -345,6 +345,10 @@ int nks_policy_label(nks_ctx* ctx, int njobs, const nks_job* jobs, double* label
  *   "min_waves"  1, 3 or 4: register budget of the stencil kernels for that
  *                many resident waves per SIMD (1 = unlimited; more waves
  *                hide more latency, fewer registers may spill)
+ *   "collapse"   >= 1 (default 1024): a pass with more workgroups per job
+ *                than this sums its per-workgroup partial sums once, in a
+ *                launch of its own, instead of in every workgroup of the
+ *                next pass (which otherwise re-reads all of them)
  *   "concurrent_groups" 1: the lattice groups of a batched call run on
  *                separate streams forked from (and joined back to) the call's
  *                stream; 0: one after another on the call's stream

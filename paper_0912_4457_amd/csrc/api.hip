@@ -50,6 +50,7 @@ struct nks_ctx {
         std::vector<char> key;
         hipGraphExec_t exec = nullptr;
         unsigned long long used = 0;
+        hipEvent_t done = nullptr;   // recorded after every launch of exec, on the launching stream
     };
     std::vector<Graph> graphs;
     unsigned long long graph_clock = 0;
@@ -262,7 +263,7 @@ int make_plan(nks_ctx* ctx, int njobs, const nks_job* jobs, Plan& P, bool label 
         jp.off_vstore = off; off = align_up(off + (size_t)(jp.ring ? 2 : jp.k) * n * es);
         jp.off_yacc = off; off = align_up(off + (jp.ring ? 2 * n * sizeof(double2) : 0));
         jp.off_lring = off; off = align_up(off + (jp.two_sided ? 2 * n * es : 0));
-        jp.off_part = off; off = align_up(off + sizeof(double2) * PS_COUNT * jp.nblocks);
+        jp.off_part = off; off = align_up(off + sizeof(double2) * PS_COUNT * (jp.nblocks + 1));
         jp.off_sc = off; off = align_up(off + sizeof(double2) * SC_COUNT * (jp.k + 2));
         jp.off_status = off; off = align_up(off + sizeof(int) * ST_COUNT);
         jp.off_report = off; off = align_up(off + sizeof(double) * RP_COUNT);
@@ -304,6 +305,8 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.lcap = jp.lcap;
     d.scstride = jp.k + 2;
     d.nblocks = jp.nblocks;
+    d.pstride = jp.nblocks + 1;   // + the collapsed total
+    d.collapse = ctx->tune.collapse;
     d.precision = jp.precision;
     d.k_policy = jp.k_policy;
     d.ell_policy = jp.ell_policy;
@@ -617,11 +620,21 @@ int enqueue_graph(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs
         if (ctx->graphs.size() >= GRAPH_CACHE) {
             auto old = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
                                         [](const nks_ctx::Graph& a, const nks_ctx::Graph& b) { return a.used < b.used; });
-            HIP_TRY(ctx, hipStreamSynchronize(s));   // an evicted graph may still be running on s
+            // the evicted graph may still run on the stream of its last launch
+            if (old->done) {
+                HIP_TRY(ctx, hipEventSynchronize(old->done));
+                (void)hipEventDestroy(old->done);
+            }
             (void)hipGraphExecDestroy(old->exec);
             ctx->graphs.erase(old);
         }
-        ctx->graphs.push_back({key, exec, 0});
+        hipEvent_t done = nullptr;
+        const hipError_t e3 = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e3 != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return fail(ctx, NKS_E_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e3));
+        }
+        ctx->graphs.push_back({key, exec, 0, done});
         hit = &ctx->graphs.back();
         ++ctx->graph_captures;
     } else {
@@ -630,6 +643,7 @@ int enqueue_graph(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs
     hit->used = ++ctx->graph_clock;
     HIP_TRY(ctx, hipMemcpyAsync(ws, descs.data(), sizeof(JobDesc) * descs.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipGraphLaunch(hit->exec, s));
+    HIP_TRY(ctx, hipEventRecord(hit->done, s));
     return NKS_OK;
 }
 
@@ -696,7 +710,6 @@ int nks_create(int device, nks_ctx** out) {
     auto* c = new nks_ctx();
     c->device = device;
     if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = std::min(3, std::max(0, atoi(e)));
-    if (const char* e = getenv("NKS_SPLIT_DUAL")) c->tune.split_dual = atoi(e) != 0;
     if (const char* e = getenv("NKS_GRAPH")) c->graph = atoi(e) != 0;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) { delete c; return NKS_E_HIP; }
@@ -714,7 +727,13 @@ void nks_destroy(nks_ctx* ctx) {
     }
     for (auto& e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->net) (void)hipFree(ctx->net);
-    for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (auto& g : ctx->graphs) {
+        if (g.done) {
+            (void)hipEventSynchronize(g.done);
+            (void)hipEventDestroy(g.done);
+        }
+        (void)hipGraphExecDestroy(g.exec);
+    }
     for (auto& st : ctx->side) (void)hipStreamDestroy(st);
     for (auto& e : ctx->join) (void)hipEventDestroy(e);
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
@@ -1175,16 +1194,19 @@ int nks_tune_set(nks_ctx* ctx, const char* key, int value) {
         if (value < 0 || value > 3) return fail(ctx, NKS_E_INVALID, "xcd_map takes 0, 1, 2 or 3");
         ctx->tune.xcd_map = value;
     } else if (k == "split_dual") ctx->tune.split_dual = value != 0;
-    else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;
+    else if (k == "min_waves") {
+        if (value != 1 && value != 3 && value != 4) return fail(ctx, NKS_E_INVALID, "min_waves takes 1, 3 or 4");
+        ctx->tune.min_waves = value;
+    } else if (k == "collapse") {
+        if (value < 1) return fail(ctx, NKS_E_INVALID, "collapse takes a block count >= 1");
+        ctx->tune.collapse = value;
+    } else if (k == "concurrent_groups") ctx->tune.concurrent = value != 0;
     else if (k == "pipeline_groups") ctx->tune.pipeline = value != 0;
     else if (k == "stagger_groups") {
         if (value < 0 || value > 100) return fail(ctx, NKS_E_INVALID, "stagger_groups takes 0..100 (percent)");
         ctx->tune.stagger = value;
     }
-    else if (k == "min_waves") {
-        if (value != 1 && value != 3 && value != 4) return fail(ctx, NKS_E_INVALID, "min_waves takes 1, 3 or 4");
-        ctx->tune.min_waves = value;
-    } else if (k == "graph") ctx->graph = value != 0;
+    else if (k == "graph") ctx->graph = value != 0;
     else return fail(ctx, NKS_E_INVALID, "unknown tuning key " + k);
     return NKS_OK;
 }
@@ -1195,6 +1217,7 @@ int nks_tune_get(nks_ctx* ctx, const char* key, int* value) {
     if (k == "xcd_map") *value = ctx->tune.xcd_map;
     else if (k == "split_dual") *value = ctx->tune.split_dual;
     else if (k == "min_waves") *value = ctx->tune.min_waves;
+    else if (k == "collapse") *value = ctx->tune.collapse;
     else if (k == "concurrent_groups") *value = ctx->tune.concurrent;
     else if (k == "pipeline_groups") *value = ctx->tune.pipeline;
     else if (k == "stagger_groups") *value = ctx->tune.stagger;

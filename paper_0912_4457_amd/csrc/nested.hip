@@ -1938,12 +1938,15 @@ __global__ __launch_bounds__(NT) void label_kernel(JobDesc* jobs) {
 // H(k,k) = alpha_k from the partial sums of the last stencil pass (the
 // recurrence pass of iteration k is not needed: App. A/B stop after it).
 __global__ __launch_bounds__(NT) void finalize_kernel(JobDesc* jobs) {
-    __shared__ double2 lds[NT / 64];
     const JobDesc& J = jobs[blockIdx.x];
     const int kused = J.status[ST_KUSED];
     if (kused == 0 || J.status[ST_DONE]) return;
     const size_t st = J.scstride;
-    const double2 s = sum_partials<NT>(J.part + (size_t)PS_S * J.nblocks, J.nblocks, lds);
+    // the last stencil pass's partials, or their total in the slot's last entry (collapsed)
+    if (threadIdx.x >= 64) return;
+    const double2* ps = J.part + (size_t)PS_S * J.pstride;
+    const bool col = J.nblocks > J.collapse;
+    const double2 s = wave_sum(col ? ps + J.pstride - 1 : ps, col ? 1 : J.nblocks);
     const double2 a = J.two_sided ? cmul(cconj(J.sc[SC_SW * st + kused]), s)
                                   : mk(J.sc[SC_SV * st + kused].x * s.x, 0.0);
     if (threadIdx.x == 0) J.sc[SC_ALPHA * st + kused] = a;

@@ -114,7 +114,9 @@ enum ReportWord {
     RP_COUNT = 16
 };
 
-// Partial-sum slots (each an array of double2 of length nblocks).
+// Partial-sum slots (each an array of double2 of length pstride: one entry per
+// block of the pass that writes it, and a last entry for their total when it
+// is collapsed).
 enum PartialSlot { PS_S = 0, PS_R0 = 1, PS_R1 = 2, PS_R2 = 3, PS_COUNT = 4 };
 
 // One sign application, as seen by the device.  Lives in the workspace.
@@ -123,7 +125,7 @@ struct JobDesc {
     double2* x;         // caller output, AoS complex128
     void* vstore;       // outer basis, (kcap + 1) columns of 12V storage-type complex, SoA
     void* lring;        // two-sided left vectors, 2 columns of 12V
-    double2* part;      // PS_COUNT * nblocks partial sums
+    double2* part;      // PS_COUNT * pstride partial sums
     double2* sc;        // SC_COUNT * (kcap + 2) scalars
     int* status;        // ST_COUNT ints
     double* report;     // RP_COUNT doubles
@@ -139,6 +141,8 @@ struct JobDesc {
     int lcap;           // inner size capacity of the nest area
     int scstride;       // length of each scalar slot (kcap + 2)
     int nblocks;        // blocks per job of the outer site-parallel kernels
+    int pstride;        // length of each partial-sum slot: nblocks + 1
+    int collapse;       // a pass with more blocks than this leaves its partials' total in the slot's last entry
     int precision;      // NKS_FP64 / NKS_MIXED
     int k_policy;       // NKS_POLICY_*
     int ell_policy;
@@ -224,12 +228,38 @@ __device__ inline double2 block_sum(double2 v, double2* lds) {
     return s;
 }
 
-// Deterministic sum of n partials (same order in every block).
-template <int NT>
+// Sum of n partial sums by the 64 lanes of one wavefront: lane l adds entries
+// l, l + 64, ..., then a butterfly over the lanes (every lane ends with the
+// same bits, addition being commutative).  The one summation order of every
+// reader of the outer passes' partial sums, so that a total summed ahead in a
+// launch of its own has the same bits.  All 64 lanes must call it.
+__device__ inline double2 wave_sum(const double2* part, int n) {
+    const int lane = threadIdx.x & 63;
+    double2 s = mk(0.0, 0.0);
+    int i = lane;
+    for (; i + 7 * 64 < n; i += 8 * 64) {   // eight loads in flight, added in index order
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = part[i + q * 64];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s = cadd(s, v[q]);
+    }
+    for (; i < n; i += 64) s = cadd(s, part[i]);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s = cadd(s, shfl_xor_d2(s, m));
+    return s;
+}
+
+// Deterministic sum of n partials (same order in every block).  NTS threads
+// take part, each summing every NTS-th partial; in a block of NTB >= NTS
+// threads the others contribute exact zeros, so the result has the bits of
+// the NTS-thread sum whatever the block size.
+template <int NTS, int NTB = NTS>
 __device__ inline double2 sum_partials(const double2* part, int n, double2* lds) {
     double2 s = mk(0.0, 0.0);
-    for (int i = threadIdx.x; i < n; i += NT) s = cadd(s, part[i]);
-    return block_sum<NT>(s, lds);
+    if (threadIdx.x < NTS)
+        for (int i = threadIdx.x; i < n; i += NTS) s = cadd(s, part[i]);
+    return block_sum<NTB>(s, lds);
 }
 
 // ----------------------------------------------------------------- launchers
@@ -243,6 +273,8 @@ struct Tuning {
     int xcd_map = 1;      // 1D grid: 1 = all jobs of a site block on one XCD, 2 = whole jobs per XCD
     int split_dual = 1;   // two-sided stencil: A u and A^dagger t in separate blocks
     int min_waves = 1;    // stencil kernels: register budget for 1 (unlimited), 3 or 4 waves per SIMD
+    int collapse = 1024;  // passes with more blocks per job than this sum their partials once in a
+                          // separate launch instead of in every block of the next pass
     int concurrent = 1;   // lattice groups of a batch on separate streams (1) or one after another (0)
     int pipeline = 0;     // with concurrent groups: each group's nested step and lift follow its own outer loop
     int stagger = 0;      // pipelined groups: the others start once the lead group has done this % of its loop
@@ -323,6 +355,7 @@ __host__ __device__ inline bool map_block(int b, int nblocks, int njobs, int xcd
 void launch_pack(const OuterLaunch& L, hipStream_t s);
 void launch_outer_S(const OuterLaunch& L, int j, hipStream_t s);   // stencil pass of iteration j
 void launch_outer_R(const OuterLaunch& L, int j, hipStream_t s);   // recurrence pass (j < k only)
+void launch_collapse(const OuterLaunch& L, int slot0, int nslots, int nb, hipStream_t s);
 void launch_lift(const OuterLaunch& L, hipStream_t s);
 
 // nested.hip

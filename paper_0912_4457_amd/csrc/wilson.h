@@ -89,12 +89,13 @@ __device__ __forceinline__ void hop(int nu, const cx_t<R> (&u)[9], const cx_t<R>
     }
 }
 
-// hop() on a neighbour spinor already in registers (same operations)
+// The half spinor that one hop contributes: h = coef * Umat (1 + SGN gamma_nu) p
+// reduced to its two upper spins (Umat = U, or U^dagger when DAG), for a
+// neighbour spinor p already in registers (same operations as hop()).
 template <int SGN, bool DAG, typename R>
-__device__ __forceinline__ void hop_pre(int nu, const cx_t<R> (&u)[9], const cx_t<R> (&p)[12], R coef,
-                                        cx_t<R> (&acc)[12]) {
+__device__ __forceinline__ void hop_half(int nu, const cx_t<R> (&u)[9], const cx_t<R> (&p)[12], R coef,
+                                         cx_t<R> (&h)[2][3]) {
     using C = cx_t<R>;
-    C h[2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         C b0, b1;
@@ -122,6 +123,27 @@ __device__ __forceinline__ void hop_pre(int nu, const cx_t<R> (&u)[9], const cx_
 #pragma unroll
         for (int a = 0; a < 3; ++a) h[s][a] = g[a];
     }
+}
+
+// Component c (= 3 spin + colour) of the full spinor of a hop's half spinor h:
+// the upper spins are h itself, the lower ones SGN B_nu^dagger h.  acc += it.
+template <typename C>
+__device__ __forceinline__ C hop_component_add(int nu, int sgn, int c, const C& h0, const C& h1, C acc) {
+    // h0, h1: h[0][colour], h[1][colour]
+    if (c < 6) return cadd(acc, c < 3 ? h0 : h1);
+    C o0, o1;
+    bdag(nu, h0, h1, o0, o1);
+    const C o = c < 9 ? o0 : o1;
+    return sgn > 0 ? cadd(acc, o) : csub(acc, o);
+}
+
+// hop() on a neighbour spinor already in registers (same operations)
+template <int SGN, bool DAG, typename R>
+__device__ __forceinline__ void hop_pre(int nu, const cx_t<R> (&u)[9], const cx_t<R> (&p)[12], R coef,
+                                        cx_t<R> (&acc)[12]) {
+    using C = cx_t<R>;
+    C h[2][3];
+    hop_half<SGN, DAG, R>(nu, u, p, coef, h);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         C o0, o1;
@@ -131,6 +153,21 @@ __device__ __forceinline__ void hop_pre(int nu, const cx_t<R> (&u)[9], const cx_
         if constexpr (SGN > 0) { acc[6 + a] = cadd(acc[6 + a], o0); acc[9 + a] = cadd(acc[9 + a], o1); }
         else { acc[6 + a] = csub(acc[6 + a], o0); acc[9 + a] = csub(acc[9 + a], o1); }
     }
+}
+
+// Neighbour of site in direction nu: forward (site + nu_hat) or backward, periodic.
+__device__ __forceinline__ int neighbour_site(const Geom& g, int site, int nu, bool forward) {
+    const int x = site % g.lx;
+    int r = site / g.lx;
+    const int y = r % g.ly;
+    r /= g.ly;
+    const int z = r % g.lz;
+    const int t = r / g.lz;
+    const int co = nu == 0 ? x : nu == 1 ? y : nu == 2 ? z : t;
+    const int ext = nu == 0 ? g.lx : nu == 1 ? g.ly : nu == 2 ? g.lz : g.lt;
+    const int st = nu == 0 ? 1 : nu == 1 ? g.lx : nu == 2 ? g.lx * g.ly : g.lx * g.ly * g.lz;
+    if (forward) return (co == ext - 1) ? site - (ext - 1) * st : site + st;
+    return (co == 0) ? site + (ext - 1) * st : site - st;
 }
 
 template <typename R>

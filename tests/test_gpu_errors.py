@@ -77,7 +77,7 @@ def test_lattice_parameters_are_validated():
         assert e.value.code == 1
     with pytest.raises(nks.NKSError):
         nks.Lattice(ctx(), (1, 4, 4, 4), I.unit_links((1, 4, 4, 4)))
-    for key, value in (("xcd_map", 4), ("min_waves", 2), ("no_such_key", 1)):
+    for key, value in (("xcd_map", 4), ("collapse", 0), ("min_waves", 2), ("no_such_key", 1)):
         with pytest.raises(nks.NKSError):
             ctx().tune_set(key, value)
 

@@ -122,13 +122,18 @@ def test_tuning_choices_are_bitwise_identical():
             dict(lat=lb, b=I.point_source((4, 4, 4, 6), 1, 2).ravel(), k=60, ell=20)]
     ref = None
     try:
-        for xm, sd, mw, cg in ((0, 0, 1, 1), (0, 1, 1, 1), (1, 0, 1, 1), (1, 1, 1, 1), (2, 0, 1, 1),
-                               (2, 1, 1, 1), (3, 0, 1, 1), (3, 1, 1, 1), (3, 1, 4, 0), (1, 1, 3, 1),
-                               (1, 0, 4, 1), (1, 1, 4, 1), (1, 1, 1, 0)):
+        # collapse = 1: every pass with more than one block per job also sums its
+        # partials ahead in a launch of its own (same order, so the same bits)
+        for xm, sd, mw, cg, col in ((0, 0, 1, 1, 1024), (0, 1, 1, 1, 1024), (1, 0, 1, 1, 1024),
+                                    (1, 1, 1, 1, 1024), (2, 0, 1, 1, 1024), (2, 1, 1, 1, 1024),
+                                    (3, 0, 1, 1, 1024), (3, 1, 1, 1, 1024), (3, 1, 4, 0, 1024),
+                                    (1, 1, 3, 1, 1024), (1, 0, 4, 1, 1024), (1, 1, 4, 1, 1024),
+                                    (1, 1, 1, 0, 1024), (1, 1, 1, 1, 1), (3, 0, 4, 0, 1), (2, 1, 1, 1, 2)):
             c.tune_set("xcd_map", xm)
             c.tune_set("split_dual", sd)
             c.tune_set("min_waves", mw)
             c.tune_set("concurrent_groups", cg)
+            c.tune_set("collapse", col)
             xs, _ = nks.sign_apply_batch(jobs)
             got = [to_np(x) for x in xs]
             if ref is None:
@@ -141,6 +146,7 @@ def test_tuning_choices_are_bitwise_identical():
         c.tune_set("split_dual", 1)
         c.tune_set("min_waves", 1)
         c.tune_set("concurrent_groups", 1)
+        c.tune_set("collapse", 1024)
 
 
 @pytest.mark.parametrize("graph", [0, 1])
