@@ -234,6 +234,26 @@ int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
                    const nks_opts* opts, void* ws, size_t ws_bytes, void* stream,
                    nks_stats* stats);
 
+/* nks_sign_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and result, but the workspace is a static array of
+ * NKS_NOALLOC_BYTES that the library holds on every GPU it runs on until the
+ * process ends (its address is taken once per GPU by nks_create), and the
+ * call makes no allocation of any kind on the device (no hipMalloc, hipFree,
+ * stream, event or graph): the job table is copied into the array and the
+ * kernels launched eagerly on `stream`.  A job whose workspace
+ * (nks_workspace_size) exceeds NKS_NOALLOC_BYTES gives NKS_E_NOMEM with the
+ * size in nks_last_error (NKS_FLAG_DOUBLE_PASS needs O(n) memory: 12 MB for
+ * one 10^4 job at k = 500).  Every call on one GPU uses the same array, which
+ * keeps the last call's contents: calls that overlap on one GPU (on
+ * different streams, or from different contexts or threads) race and must
+ * be ordered by the caller.  Nothing needs clearing between calls (the
+ * kernels initialise what they read).  If stats != NULL the call waits for
+ * the stream and fills *stats. */
+#define NKS_NOALLOC_BYTES (64u << 20)
+int nks_sign_apply_noalloc(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
+                           const nks_opts* opts, void* stream, nks_stats* stats);
+
 /* Many jobs in one call: jobs on the same lattice share each stencil sweep
  * over the links.  In graph mode (the default, tuning key "graph") a call
  * without stats and without profiling captures its whole launch sequence

@@ -98,6 +98,7 @@ SIGNATURES = {
     "nks_workspace_size": (_I, [_VP, _I, ctypes.POINTER(Job), ctypes.POINTER(_SZ)]),
     "nks_sign_apply": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
     "nks_sign_apply_batch": (_I, [_VP, _I, ctypes.POINTER(Job), _VP, _SZ, _VP, ctypes.POINTER(Stats)]),
+    "nks_sign_apply_noalloc": (_I, [_VP, _VP, _VP, _VP, ctypes.POINTER(Opts), _VP, ctypes.POINTER(Stats)]),
     "nks_outer_basis": (_I, [_VP, _VP, _VP, ctypes.POINTER(Opts), _VP, _SZ, _VP, _PD, _PD, _PD,
                              ctypes.POINTER(Stats)]),
     "nks_nested_step": (_I, [_VP, _I, _PD, _PD, _PD, _I, ctypes.POINTER(Opts), _PD, ctypes.POINTER(Stats)]),
@@ -383,6 +384,22 @@ def sign_apply(lat: Lattice, b, k: int = 200, ell: int = 50, p: float | None = N
     ctx.check(lib().nks_sign_apply(ctx.h, lat.h, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                    ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(),
                                    ctypes.byref(st) if stats else None))
+    return x, (st.as_dict() if stats else None)
+
+
+def sign_apply_noalloc(lat: Lattice, b, k: int = 200, ell: int = 50, p: float | None = None, precision="fp64",
+                       tol: float = 1e-8, stats: bool = True, out=None, **kw):
+    """sign_apply with the library's static per-GPU workspace (nks_sign_apply_noalloc):
+    no device allocation in the call; returns (x, stats dict or None)."""
+    torch = _torch()
+    b = _vec(lat, b)
+    x = torch.empty_like(b) if out is None else out
+    o = make_opts(k=k, ell=ell, tol=tol, precision=precision, p=p, **kw)
+    st = Stats()
+    ctx = lat.ctx
+    ctx.check(lib().nks_sign_apply_noalloc(ctx.h, lat.h, ctypes.c_void_p(b.data_ptr()),
+                                           ctypes.c_void_p(x.data_ptr()), ctypes.byref(o), _stream(),
+                                           ctypes.byref(st) if stats else None))
     return x, (st.as_dict() if stats else None)
 
 

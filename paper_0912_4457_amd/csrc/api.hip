@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,29 @@
 namespace {
 constexpr int EIG_DEGREE = 40;                    // Chebyshev filter degree of the eigensolver
 constexpr unsigned long long EIG_SEED = 20091224;  // its start block
+
+// Workspace of nks_sign_apply_noalloc, for callers that cannot allocate: one
+// array of NKS_NOALLOC_BYTES on every GPU the library runs on, held from when
+// the library's code object is loaded until the process ends.  In host code
+// the name `scratch` is only a stand-in: its device address on each GPU is
+// taken once, by nks_create with that GPU current, into g_scratch[device].
+static __device__ __align__(256) char scratch[NKS_NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+void* g_scratch[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// Device address of the calling GPU's scratch array; the GPU must be current.
+int scratch_address(int device, void** out) {
+    if (device < 0 || device >= MAX_DEVICES) return NKS_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NKS_E_HIP;
+        g_scratch[device] = p;
+    }
+    *out = g_scratch[device];
+    return NKS_OK;
+}
 }  // namespace
 
 using namespace nks;
@@ -707,6 +731,8 @@ int nks_create(int device, nks_ctx** out) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return NKS_E_INVALID;
     if (hipSetDevice(device) != hipSuccess) return NKS_E_HIP;
+    void* scr = nullptr;
+    if (const int rc = scratch_address(device, &scr)) return rc;
     auto* c = new nks_ctx();
     c->device = device;
     if (const char* e = getenv("NKS_XCD_MAP")) c->tune.xcd_map = std::min(3, std::max(0, atoi(e)));
@@ -972,6 +998,39 @@ int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x, const
                    size_t ws_bytes, void* stream, nks_stats* stats) {
     nks_job j{lat, b, x, opts};
     return nks_sign_apply_batch(ctx, 1, &j, ws, ws_bytes, stream, stats);
+}
+
+int nks_sign_apply_noalloc(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x, const nks_opts* opts, void* stream,
+                           nks_stats* stats) {
+    if (!ctx || !lat || !b || !x) return fail(ctx, NKS_E_INVALID, "NULL argument");
+    nks_job j{lat, b, x, opts};
+    Plan P;
+    int rc = make_plan(ctx, 1, &j, P);
+    if (rc) return rc;
+    if (P.total > (size_t)NKS_NOALLOC_BYTES)
+        return fail(ctx, NKS_E_NOMEM,
+                    "nks_sign_apply_noalloc: this job needs " + std::to_string(P.total) +
+                        " bytes of workspace, more than the NKS_NOALLOC_BYTES (" + std::to_string(NKS_NOALLOC_BYTES) +
+                        ") the library holds per GPU; use NKS_FLAG_DOUBLE_PASS (O(n) memory) or nks_sign_apply "
+                        "with a workspace of nks_workspace_size bytes");
+    void* ws = nullptr;
+    if (scratch_address(ctx->device, &ws)) return fail(ctx, NKS_E_HIP, "no scratch address for this GPU");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    char* w = static_cast<char*>(ws);
+    std::vector<JobDesc>& descs = ctx->descs;
+    descs.clear();
+    descs.push_back(make_desc(ctx, P, P.jobs[0], w, b, x));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // eager launches on the caller's stream only: one job is one lattice group,
+    // so no side stream, no graph and nothing else is created or allocated
+    rc = enqueue(ctx, P, descs, w, s, stats != nullptr, PH_ALL);
+    if (rc) return rc;
+    if (stats) {
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        rc = read_stats(ctx, P, w, true, stats);
+        if (rc) return rc;
+    }
+    return NKS_OK;
 }
 
 int nks_outer_basis(nks_ctx* ctx, nks_lattice* lat, const void* b, const nks_opts* opts, void* ws, size_t ws_bytes,
