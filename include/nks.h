@@ -254,8 +254,11 @@ int nks_sign_apply(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
 int nks_sign_apply_noalloc(nks_ctx* ctx, nks_lattice* lat, const void* b, void* x,
                            const nks_opts* opts, void* stream, nks_stats* stats);
 
-/* Many jobs in one call: jobs on the same lattice share each stencil sweep
- * over the links.  In graph mode (the default, tuning key "graph") a call
+/* Many jobs in one call: jobs on the same lattice (and precision) run in the
+ * same stencil and recurrence launches, one workgroup per (site block, job)
+ * (each reads the links of its site block itself; launch maps 1 and 3 put
+ * the jobs of a site block on one XCD, so that those reads can be served by
+ * its L2).  In graph mode (the default, tuning key "graph") a call
  * without stats and without profiling captures its whole launch sequence
  * into a HIP graph on a private stream, keyed by the job table (every
  * pointer, size and option) and the workspace address, and later calls

@@ -407,7 +407,8 @@ def sign_apply_batch(jobs, stats: bool = True, workspace=None):
     """jobs: list of dicts {lat, b, k, ell, p, precision} (or with 'x').
 
     All jobs run in one call on the current torch stream; jobs on the same
-    lattice share each stencil sweep.  ``workspace``: a device uint8 tensor
+    lattice run in the same stencil launches (each workgroup reads its own
+    links).  ``workspace``: a device uint8 tensor
     of at least nks_workspace_size bytes (default: the context's own), so
     that batches can be in flight on several streams at once.  Returns (list
     of x tensors, list of stats dicts or None)."""

@@ -21,12 +21,13 @@
 #include <sanitizer/asan_interface.h>
 
 #include <cstdio>
+#include <cstring>
 #include <vector>
 
 namespace {
 
 enum Hdr { H_K, H_ELL, H_TWO_SIDED, H_KUSED, H_MAX_RHI, H_MODE, H_I_LO, H_I_HI, H_V, H_KPOL, H_ELLPOL, H_LEVELS,
-           H_NO_HEAD, H_COUNT = 16 };
+           H_NO_HEAD, H_FILL, H_COUNT = 16 };
 enum Par { P_P, P_TOL, P_RHI_TOL, P_MU, P_BNORM, P_COUNT = 8 };
 
 template <typename T>
@@ -103,6 +104,17 @@ int main(int argc, char** argv) {
     d.nest = alloc<double2>(nw * nareas);
     d.status[ST_KUSED] = h[H_KUSED];
     d.report[RP_BNORM] = par[P_BNORM];
+    // device workspace is not cleared by the library: fill what the kernels
+    // must write before reading with a byte pattern (H_FILL != 0), so that a
+    // read of unwritten memory gives garbage here too rather than zeros
+    if (h[H_FILL]) {
+        const int fb = h[H_FILL] & 0xFF;
+        memset(d.nest, fb, sizeof(double2) * nw * nareas);
+        memset(d.omega, fb, sizeof(double2) * k);
+        memset(d.part, fb, sizeof(double2) * PS_COUNT);
+        if (d.label) memset(d.label, fb, sizeof(double) * LABEL_WORDS);
+        if (d.ckpt && cref.empty()) memset(d.ckpt, fb, sizeof(double2) * k);
+    }
     JobDesc* table = alloc<JobDesc>(1);
     table[0] = d;
 

@@ -47,11 +47,12 @@ def build(out_dir: str, asan: bool = True, tsan: bool = False) -> str:
 def run(exe: str, alpha, beta, gamma, hermitian: bool, ell: int, *, vnorm=None, p: float = 0.0,
         mode: int = NEST_FINAL, label_points=(0, 0), tol: float = 1e-8, ell_policy: int = POLICY_FIXED,
         max_rhi: int = 50, rhi_tol: float = 1e-14, V: int = 256, mu: float = 0.0, timeout: float = 3600,
-        label_head: bool = True, c_ref=None):
+        label_head: bool = True, c_ref=None, fill: int = 0):
     """Runs one job; returns dict(status, report, c, label).  c = sgn(H_k) e_1
     as the kernel computes it (omega with |b| = 1 and unit scale factors).
     Label mode: label_head=False skips the launch that computes the features
-    and the reference coefficients, which then come from c_ref."""
+    and the reference coefficients, which then come from c_ref.  fill: a
+    byte (1..255) written over the scratch buffers before the launch (0: zeros)."""
     alpha = np.asarray(alpha, dtype=np.complex128)
     k = alpha.size
     sc = np.zeros((SC_COUNT, k + 2), dtype=np.complex128)
@@ -63,8 +64,8 @@ def run(exe: str, alpha, beta, gamma, hermitian: bool, ell: int, *, vnorm=None, 
     sc[SC_VN, 1:k + 1] = 1.0 if vnorm is None else np.asarray(vnorm, dtype=np.float64)
     sc[SC_WN, 1:k + 1] = 1.0
     hdr = np.zeros(16, dtype=np.int32)
-    hdr[:13] = [k, ell, 0 if hermitian else 1, k, max_rhi, mode, label_points[0], label_points[1], V,
-                POLICY_FIXED, ell_policy, 1, 0 if label_head else 1]
+    hdr[:14] = [k, ell, 0 if hermitian else 1, k, max_rhi, mode, label_points[0], label_points[1], V,
+                POLICY_FIXED, ell_policy, 1, 0 if label_head else 1, fill]
     par = np.zeros(8, dtype=np.float64)
     par[:5] = [p, tol, rhi_tol, mu, 1.0]
     with tempfile.TemporaryDirectory() as td:

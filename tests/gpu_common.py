@@ -54,3 +54,22 @@ def operator(dims, eps, seed, mu, kind="su3"):
 
 def to_np(t):
     return t.detach().cpu().numpy()
+
+
+def rounding_tolerance(run, b, hermitian, floor=1e-10, factor=10.0, draws=3):
+    """(tolerance, response) for a GPU result that equals the oracle's run(b)
+    up to rounding.  Hermitian runs take ``floor``.  Two-sided runs (Eq.
+    non-nested-oblique, App. B) amplify rounding well beyond that, so any
+    other rounding order lands further than 1e-10 away: their tolerance is
+    ``factor`` times the oracle's own response to two-ulp componentwise
+    changes of the source (the size of one rounding), at least ``floor``."""
+    if hermitian:
+        return floor, 0.0
+    b = np.asarray(b, dtype=np.complex128)
+    y0 = np.ravel(run(b))
+    resp = 0.0
+    for s in range(draws):
+        rng = np.random.default_rng(7100 + s)
+        bp = b * (1 + 4e-16 * rng.choice([-1.0, 1.0], b.shape))
+        resp = max(resp, rel(run(bp), y0))
+    return max(floor, factor * resp), resp

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import nks_inputs as I
-from gpu_common import ctx, lattice, operator, rel, to_np
+from gpu_common import ctx, lattice, operator, rel, rounding_tolerance, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +83,11 @@ def test_double_pass_matches_oracle(mu, k, ell):
     y_ref, info = nested.sign_apply(op, b, k, ell)
     x, st = nks.sign_apply(lat, b.ravel(), k=k, ell=ell, p=info["p"], double_pass=True)
     assert st["status"] == 0 and st["k_used"] == info["k"]
-    assert rel(to_np(x), y_ref) <= 1e-9
+    err = rel(to_np(x), y_ref)
+    tol, resp = rounding_tolerance(lambda v: nested.sign_apply(op, v, k, ell, p=info["p"])[0], b, mu == 0.0)
+    print(f"mu={mu} k={k} ell={ell}: double pass vs oracle (same k, ell, p) {err:.2e}, tolerance {tol:.1e} "
+          f"(oracle's rounding response {resp:.1e})")
+    assert err <= tol
 
 
 def test_double_pass_degenerate_sources():
