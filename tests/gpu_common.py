@@ -61,8 +61,10 @@ def rounding_tolerance(run, b, hermitian, floor=1e-10, factor=10.0, draws=3):
     up to rounding.  Hermitian runs take ``floor``.  Two-sided runs (Eq.
     non-nested-oblique, App. B) amplify rounding well beyond that, so any
     other rounding order lands further than 1e-10 away: their tolerance is
-    ``factor`` times the oracle's own response to two-ulp componentwise
-    changes of the source (the size of one rounding), at least ``floor``."""
+    ``factor`` times the oracle's own response to two-ulp changes of every
+    component of the source (relative to the entry, plus the same relative to
+    the source's rms entry, so that a point source is not merely rescaled),
+    at least ``floor``."""
     if hermitian:
         return floor, 0.0
     b = np.asarray(b, dtype=np.complex128)
@@ -70,6 +72,7 @@ def rounding_tolerance(run, b, hermitian, floor=1e-10, factor=10.0, draws=3):
     resp = 0.0
     for s in range(draws):
         rng = np.random.default_rng(7100 + s)
-        bp = b * (1 + 4e-16 * rng.choice([-1.0, 1.0], b.shape))
+        rms = float(np.linalg.norm(b)) / np.sqrt(b.size)
+        bp = b * (1 + 4e-16 * rng.choice([-1.0, 1.0], b.shape)) + 4e-16 * rms * rng.choice([-1.0, 1.0], b.shape)
         resp = max(resp, rel(run(bp), y0))
     return max(floor, factor * resp), resp
