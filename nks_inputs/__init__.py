@@ -160,6 +160,20 @@ _CONFIGS = {
 }
 
 
+def sketch_rows(n: int, rows, seed: int) -> np.ndarray:
+    """Rows ``rows`` (an iterable of row indices) of a seeded complex Gaussian
+    sketch matrix S of shape (total rows, n) with E|S_ij|^2 = 1; each row is
+    drawn from its own generator, so any subset of rows is reproducible on
+    its own.  For a vector e, |S e|^2 / (number of rows) estimates |e|^2 (a
+    chi-square with 2 * rows degrees of freedom: with 256 rows the estimate of
+    |e| has a relative spread of about 3 %)."""
+    out = []
+    for i in rows:
+        rng = np.random.default_rng([seed, int(i)])
+        out.append((rng.standard_normal(n) + 1j * rng.standard_normal(n)) * np.sqrt(0.5))
+    return np.array(out)
+
+
 def config(name: str) -> dict:
     """A copy of one named synthetic workload description."""
     return dict(_CONFIGS[name])
