@@ -91,7 +91,10 @@ typedef struct nks_opts {
     double tol;           /* target relative accuracy for the policies */
     int precision;        /* enum nks_precision */
     double p;             /* preconditioner factor of Eq. precond; <= 0 -> p_opt of Eq. popt
-                             estimated from the Ritz values of H_k */
+                             estimated from the Ritz values of H_k, with z_max capped at
+                             1 + kappa (6 sqrt 2 + 2 sqrt(2 cosh 2 mu)) >= ||A|| (a larger
+                             |theta| is a spurious two-sided Ritz value); nks_nested_step,
+                             which has no lattice, does not cap */
     int k_policy;         /* enum nks_policy */
     int ell_policy;       /* enum nks_policy */
     int max_rhi_iter;     /* Roberts-Higham iteration cap (default 50) */
@@ -138,7 +141,8 @@ typedef struct nks_stats {
     int ell_used;         /* inner basis size actually used (0 = non-nested) */
     int rhi_iters;        /* Roberts-Higham iterations */
     double p_used;        /* preconditioner factor used */
-    double z_min, z_max;  /* Ritz-value extremes |theta| used for p (0 if p was given) */
+    double z_min, z_max;  /* Ritz-value extremes |theta| used for p, z_max after the cap
+                             above (0 if p was given) */
     double b_norm;        /* |b| */
     int breakdown_iter;   /* iteration of a serious breakdown, else 0 */
     double inner_delta;   /* last ell-doubling relative change (policies), else 0 */

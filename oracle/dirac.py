@@ -123,6 +123,18 @@ def hermitian_wilson_csr(links, dims, m0: float, mu: float) -> sp.csr_matrix:
     return (gamma5_full(V) @ d).tocsr()
 
 
+def norm_bound(m0: float, mu: float) -> float:
+    """Upper bound of ||A|| = ||D_w(mu)|| (Sec. 2), hence of every |lambda| of A.
+
+    D_w = 1 - kappa sum_nu (c_+ (1 - gamma_nu) U S_+ + c_- (1 + gamma_nu) U^dag S_-)
+    with shifts S_+-, c_+- = 1 in space and e^{+-mu} in time.  (1 -+ gamma_nu)/2
+    are complementary orthogonal projectors and U S_+- are unitary, so each
+    direction's hop term has norm <= 2 kappa sqrt(c_+^2 + c_-^2): 2 sqrt(2) kappa
+    in space, 2 sqrt(2 cosh 2mu) kappa in time."""
+    kappa = kappa_from_m0(m0)
+    return 1.0 + kappa * (6.0 * np.sqrt(2.0) + 2.0 * np.sqrt(2.0 * np.cosh(2.0 * mu)))
+
+
 class Operator:
     """A = gamma5 D_w(mu) with both A v and A^dagger v (CSR conjugate transpose)."""
 
@@ -130,6 +142,7 @@ class Operator:
         self.dims = tuple(int(d) for d in dims)
         self.m0 = float(m0)
         self.mu = float(mu)
+        self.norm_bound = norm_bound(self.m0, self.mu)
         self.A = hermitian_wilson_csr(links, self.dims, m0, mu)
         self.AH = self.A.conj().T.tocsr()
         self.n = self.A.shape[0]

@@ -40,14 +40,14 @@ def _tridiag_dense(alpha, beta, gamma):
     return h
 
 
-def _level(alpha, beta, gamma, hermitian, size, p):
+def _level(alpha, beta, gamma, hermitian, size, p, zmax_bound=None):
     """One level: Lanczos on T' from e_1 with ``size`` steps.
 
     Returns (inner Krylov result, p used, z_min, z_max)."""
     k = len(alpha)
     zmin = zmax = None
     if p is None or p <= 0:
-        zmin, zmax = ritz_extremes(alpha, beta, gamma, hermitian)
+        zmin, zmax = ritz_extremes(alpha, beta, gamma, hermitian, zmax_bound)
         p = p_opt(zmin, zmax)
     p = float(p)
     lu = TridiagLU(p * beta, p * alpha, p * gamma)
@@ -70,10 +70,12 @@ def _level(alpha, beta, gamma, hermitian, size, p):
 
 
 def multilevel_coefficients(alpha, beta, gamma, hermitian: bool, sizes, ps=None,
-                            force_nested: bool = False):
+                            force_nested: bool = False, zmax_bound: float | None = None):
     """c ~ sgn(T_0) e_1 for the tridiagonal T_0 = H_k by ``len(sizes)`` nested
     levels; ``sizes[i]`` = k_{i+1} (rounded up to even), ``ps[i]`` = p_i
-    (None or <= 0: p_opt from the Ritz values of T_i).
+    (None or <= 0: p_opt from the Ritz values of T_i; at level 0 with z_max
+    capped at ``zmax_bound``, a bound of A's spectrum, as in the one-level
+    method; the deeper T_i have their own spectra).
 
     Returns (c, info); info holds the sizes and p of the levels that ran,
     the RHi iterations at the deepest level and a status."""
@@ -93,7 +95,7 @@ def multilevel_coefficients(alpha, beta, gamma, hermitian: bool, sizes, ps=None,
         k = len(a)
         if size >= k and not force_nested:
             break                                       # level i is exact: RHi on T_i
-        inner, p, zmin, zmax = _level(a, b, g, hermitian, min(size, k), ps[i])
+        inner, p, zmin, zmax = _level(a, b, g, hermitian, min(size, k), ps[i], zmax_bound if i == 0 else None)
         info["p"].append(p)
         info["z_min"].append(zmin)
         info["z_max"].append(zmax)
@@ -125,7 +127,8 @@ def sign_apply(op, x, k: int, sizes, ps=None, force_nested: bool = False):
         kr = krylov.two_sided_lanczos(op.matvec, op.rmatvec, xf, k)
     if kr.status == "zero":
         return np.zeros_like(x), dict(sizes=[0], p=[], status="ok", levels=0)
-    c, info = multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, op.hermitian, sizes, ps, force_nested)
+    c, info = multilevel_coefficients(kr.alpha, kr.beta, kr.gamma, op.hermitian, sizes, ps, force_nested,
+                                      zmax_bound=op.norm_bound)
     info["k"] = kr.k_used
     if kr.status == "breakdown":
         info["status"] = "breakdown"

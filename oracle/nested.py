@@ -72,9 +72,15 @@ def tridiag_matvec(sub, diag, sup, v):
     return y
 
 
-def ritz_extremes(alpha, beta, gamma, hermitian: bool):
+def ritz_extremes(alpha, beta, gamma, hermitian: bool, zmax_bound: float | None = None):
     """(z_min, z_max) of the Ritz values of H_k, the spectrum estimate behind
     p_opt of Sec. 4.1 (Eq. popt).
+
+    Eq. popt wants the extremes of A's spectrum.  With ``zmax_bound`` (a bound
+    of |lambda| over A's spectrum, ``dirac.norm_bound``) z_max is capped
+    there: a larger |theta| cannot belong to A.  Hermitian Ritz values never
+    exceed it; a two-sided H_k without reorthogonalisation can hold a
+    spurious one far outside A's spectrum, which would mistune p.
 
     z_max = max |theta|.  Hermitian: z_min is the second smallest |theta|.
     The Ritz values of a Krylov space are the zeros of the Lanczos
@@ -92,13 +98,16 @@ def ritz_extremes(alpha, beta, gamma, hermitian: bool):
             w = sla.eigh_tridiagonal(np.asarray(alpha, float), np.asarray(beta, float),
                                      eigvals_only=True)
         z = np.sort(np.abs(w))
-        return float(z[1] if z.size > 1 else z[0]), float(z[-1])
-    k = len(alpha)
-    h = np.diag(np.asarray(alpha, complex))
-    if k > 1:
-        h += np.diag(np.asarray(beta, complex), -1) + np.diag(np.asarray(gamma, complex), 1)
-    z = np.sort(np.abs(np.linalg.eigvals(h)))
-    return float(z[1] if z.size > 1 else z[0]), float(z[-1])
+    else:
+        k = len(alpha)
+        h = np.diag(np.asarray(alpha, complex))
+        if k > 1:
+            h += np.diag(np.asarray(beta, complex), -1) + np.diag(np.asarray(gamma, complex), 1)
+        z = np.sort(np.abs(np.linalg.eigvals(h)))
+    zmax = float(z[-1])
+    if zmax_bound is not None:
+        zmax = min(zmax, float(zmax_bound))
+    return float(z[1] if z.size > 1 else z[0]), zmax
 
 
 class NestedInfo(dict):
@@ -106,12 +115,14 @@ class NestedInfo(dict):
 
 
 def nested_coefficients(alpha, beta, gamma, hermitian: bool, ell: int, p: float | None = None,
-                        precondition: bool = True, force_nested: bool = False):
+                        precondition: bool = True, force_nested: bool = False,
+                        zmax_bound: float | None = None):
     """Steps 3-5: c ~ sgn(H_k) e_1^{(k)} from the tridiagonal H_k.
 
     Returns (c, info).  ``ell`` is rounded up to even; ``ell >= k`` runs the
     non-nested RHi on H_k unless ``force_nested``.  ``precondition=False``
     uses the plain inner space K_ell(H_k, e_1) of Sec. 4.1 (for tests).
+    ``zmax_bound`` caps z_max of the p_opt estimate (``ritz_extremes``).
     """
     k = len(alpha)
     ell = krylov.even_up(ell)
@@ -137,7 +148,7 @@ def nested_coefficients(alpha, beta, gamma, hermitian: bool, ell: int, p: float 
     e1[0] = 1.0
     if precondition:
         if p is None:
-            zmin, zmax = ritz_extremes(alpha, beta, gamma, hermitian)
+            zmin, zmax = ritz_extremes(alpha, beta, gamma, hermitian, zmax_bound)
             info.update(z_min=zmin, z_max=zmax)
             p = p_opt(zmin, zmax)
         p = float(p)
@@ -188,7 +199,7 @@ def sign_apply(op, x, k: int, ell: int, p: float | None = None,
         info = NestedInfo(k=0, ell=0, status="ok", p=None, rhi_iters=0, nested=False)
         return np.zeros(shape, np.complex128), info
     c, info = nested_coefficients(kr.alpha, kr.beta, kr.gamma, op.hermitian, ell, p,
-                                  precondition, force_nested)
+                                  precondition, force_nested, zmax_bound=op.norm_bound)
     info["k"] = kr.k_used
     info["outer_status"] = kr.status
     if kr.status == "breakdown":

@@ -27,8 +27,9 @@ DK = 100
 
 
 def ell_doubling(alpha, beta, gamma, hermitian: bool, tol: float, ell_max: int | None = None,
-                 p: float | None = None):
-    """Returns (c, info) with info['ell'] (0 if non-nested) and info['inner_delta']."""
+                 p: float | None = None, zmax_bound: float | None = None):
+    """Returns (c, info) with info['ell'] (0 if non-nested) and info['inner_delta'];
+    ``zmax_bound`` caps z_max of the p_opt estimate (``nested.ritz_extremes``)."""
     k = len(alpha)
     cap = k if ell_max is None else min(int(ell_max), k)
     ell = ELL0
@@ -36,17 +37,17 @@ def ell_doubling(alpha, beta, gamma, hermitian: bool, tol: float, ell_max: int |
         c, info = nested_coefficients(alpha, beta, gamma, hermitian, k)
         info["inner_delta"] = 0.0
         return c, info
-    c_prev, info = nested_coefficients(alpha, beta, gamma, hermitian, ell, p)
+    c_prev, info = nested_coefficients(alpha, beta, gamma, hermitian, ell, p, zmax_bound=zmax_bound)
     while True:
         ell2 = 2 * ell
         if ell2 >= cap:
             if cap >= k:
                 c, info = nested_coefficients(alpha, beta, gamma, hermitian, k)
             else:
-                c, info = nested_coefficients(alpha, beta, gamma, hermitian, cap, p)
+                c, info = nested_coefficients(alpha, beta, gamma, hermitian, cap, p, zmax_bound=zmax_bound)
             info["inner_delta"] = float(np.linalg.norm(c - c_prev) / np.linalg.norm(c))
             return c, info
-        c, info = nested_coefficients(alpha, beta, gamma, hermitian, ell2, p)
+        c, info = nested_coefficients(alpha, beta, gamma, hermitian, ell2, p, zmax_bound=zmax_bound)
         delta = float(np.linalg.norm(c - c_prev) / np.linalg.norm(c))
         if delta <= tol / 10:
             info["inner_delta"] = delta
@@ -75,7 +76,8 @@ def sign_apply_policy(op, x, tol: float, k_max: int, ell_max: int | None = None,
     while True:
         kk = min(k, kr.k_used)
         sl = slice(0, kk)
-        c, info = ell_doubling(kr.alpha[sl], kr.beta[:kk - 1], kr.gamma[:kk - 1], op.hermitian, tol, ell_max)
+        c, info = ell_doubling(kr.alpha[sl], kr.beta[:kk - 1], kr.gamma[:kk - 1], op.hermitian, tol, ell_max,
+                               zmax_bound=op.norm_bound)
         if c_prev is not None:
             d = c.copy()
             d[:len(c_prev)] -= c_prev

@@ -338,6 +338,7 @@ JobDesc make_desc(const nks_ctx* ctx, const Plan& P, const JobPlan& jp, char* ws
     d.ckpt = (jp.k_policy != NKS_POLICY_FIXED || jp.label) ? reinterpret_cast<double2*>(ws + jp.off_ckpt) : nullptr;
     d.label = jp.label ? reinterpret_cast<double*>(ws + jp.off_label) : nullptr;
     d.mu = jp.lat->mu;
+    d.zcap = norm_bound(jp.lat->kappa, jp.lat->mu);
     d.V = jp.lat->g.V;
     d.net = jp.learned() ? ctx->net : nullptr;
     d.group = reinterpret_cast<int*>(ws + P.group_off) + (size_t)GROUP_WORDS * jp.group;

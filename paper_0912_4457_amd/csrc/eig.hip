@@ -353,10 +353,7 @@ int eig_chfsi(const Geom& g, const double2* links, double kappa, double mu, int 
         err = "eigensolver: device allocation failed";
         return NKS_E_NOMEM;
     }
-    // ||A|| <= 1 + kappa (6 sqrt(2) + 2 sqrt(2 cosh 2mu)): per direction the two hops
-    // land in the complementary ranges of (1 - gamma)/2 and (1 + gamma)/2, so their sum
-    // has norm <= 2 sqrt(c_+^2 + c_-^2) for hop factors c_+, c_- (1, or e^{+mu}, e^{-mu} in t)
-    const double na = 1.0 + kappa * (6.0 * std::sqrt(2.0) + 2.0 * std::sqrt(2.0 * std::cosh(2.0 * mu)));
+    const double na = norm_bound(kappa, mu);     // ||A||, so ||A^2|| <= na^2
     const double bound = na * na;
     const bool hermitian = mu == 0.0;
     std::vector<cd> th;

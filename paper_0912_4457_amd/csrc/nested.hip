@@ -1573,6 +1573,10 @@ __device__ NestResult nested_coeffs(const JobDesc& J, const NestPtrs& P, int kk,
     double p = J.p;
     if (p <= 0.0) {
         estimate_extremes<T>(P, kk, sm, res.zmin, res.zmax);
+        // no eigenvalue of A lies beyond J.zcap: a larger |theta| is a spurious
+        // Ritz value of the oblique projection (two-sided, without
+        // reorthogonalisation), and taking it for z_max would mistune p
+        if (J.zcap > 0.0 && res.zmax > J.zcap) res.zmax = J.zcap;
         p = 1.0 / sqrt(res.zmin * res.zmax);
         if (!(p > 0.0) || !isfinite(p)) p = 1.0;   // degenerate estimate: p = 1 is one RHi step
     }

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include <string>
 
 #include "../../include/nks.h"
@@ -149,6 +151,8 @@ struct JobDesc {
     double tol;         // target relative accuracy of the policies
     double2* ckpt;      // coefficients of the last k-checkpoint (kcap)
     double mu;          // chemical potential of the job's lattice
+    double zcap;        // bound of |lambda| over A's spectrum (norm_bound); z_max of Eq. popt is
+                        // capped there (a larger |theta| of H_k is spurious); <= 0: no cap
     int V;              // lattice volume
     const struct PolicyNet* net;   // learned policy (device), or null
     double* label;      // label mode output (LABEL_WORDS doubles), or null
@@ -305,6 +309,14 @@ struct OuterLaunch {
     LaunchEvents ev;       // timing of the next S, R or lift launch
 };
 constexpr int OUTER_NT = 128;
+
+// ||A|| = ||D_w(mu)|| <= 1 + kappa (6 sqrt(2) + 2 sqrt(2 cosh 2 mu)) (Sec. 2 operator):
+// per direction the two hops land in the complementary ranges of (1 -+ gamma_nu)/2,
+// so their sum has norm <= 2 kappa sqrt(c+^2 + c-^2) with hop factors c+- = 1, or
+// e^{+-mu} in time.  Every eigenvalue of A lies in |lambda| <= this bound.
+inline double norm_bound(double kappa, double mu) {
+    return 1.0 + kappa * (6.0 * std::sqrt(2.0) + 2.0 * std::sqrt(2.0 * std::cosh(2.0 * mu)));
+}
 
 // Launch map of the outer passes (tuning key xcd_map).  The hardware hands
 // workgroup b of a 1D grid to XCD b % 8, so b -> (site block, job) decides

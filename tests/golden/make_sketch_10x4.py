@@ -9,8 +9,8 @@ make_point12_10x4.py) is stored as S y, with S the 256-row seeded complex
 Gaussian sketch of ``nks_inputs.sketch_rows``, together with |y|: then
 |S x - S y| / (16 |y|) estimates the full-vector relative error of any
 result x to about 3 %.  The file also holds the oracle's own full-vector
-errors (exact, not sketched) at a range of outer sizes k, without nesting and
-with the nested method at ell = 64, which fix the smallest k at which the
+errors (exact, not sketched) at outer sizes k = 440 ... 700, without nesting
+and with the nested method at ell = 64 (p as in a sign application), which fix the smallest k at which the
 method itself reaches a given accuracy on this workload.
 
 Calls only ``oracle`` and ``nks_inputs``.  About an hour with 5 single-threaded
@@ -32,7 +32,7 @@ from make_point12_10x4 import DIMS, K_CHECK, K_REF, sign_e1  # noqa: E402
 from oracle import dirac, krylov, nested  # noqa: E402
 
 ROWS, SEED = 256, 20261204
-KS = (440, 460, 480, 500, 520, 540, 560, 580, 600, 620)
+KS = tuple(range(440, 701, 20))
 ELL = 64
 
 
@@ -58,7 +58,7 @@ def one_source(case):
         a, be, ga = kr.alpha[:k], kr.beta[:k - 1], kr.gamma[:k - 1]
         yk = kr.bnorm * (kr.V[:, :k] @ sign_e1(a, be, ga, herm))
         e_plain.append(float(np.linalg.norm(yk - y)) / ny)
-        c, _ = nested.nested_coefficients(a, be, ga, herm, ELL)
+        c, _ = nested.nested_coefficients(a, be, ga, herm, ELL, zmax_bound=op.norm_bound)
         e_nested.append(float(np.linalg.norm(kr.bnorm * (kr.V[:, :k] @ c) - y)) / ny)
     sy = I.sketch_rows(n, range(ROWS), SEED) @ y
     print(f"mu={mu} spin={spin} colour={colour}: change {change:.1e}, nested ell={ELL} errors "

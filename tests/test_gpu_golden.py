@@ -62,9 +62,14 @@ def test_point12_10x4_matches_oracle(precision, tol):
     # true error by tol with a margin of five spreads) and the sampled entries
     sk = bench.errors_vs_sketch(jobs, xs, bench.sketch_golden())
     assert sk is not None and len(sk) == 24
-    for (mu, spin, colour, e) in ferrs:
+    # the two files hold separate oracle runs of the same reference, each accurate
+    # to its change_from_k_check: at errors near that level the two differ by it
+    sg = bench.sketch_golden()
+    for i, (mu, spin, colour, e) in enumerate(ferrs):
         est = next(s for j, s in zip(jobs, sk) if (j["mu"], j["spin"], j["colour"]) == (mu, spin, colour))
-        assert abs(est - e) <= 0.15 * e, (mu, spin, colour, est, e)
+        t = [c for c in range(24) if (sg["mu"][c], sg["spin"][c], sg["colour"][c]) == (mu, spin, colour)][0]
+        slack = 2 * max(float(full["change_from_k_check"][i]), float(sg["change_from_k_check"][t]))
+        assert abs(est - e) <= 0.15 * e + slack, (mu, spin, colour, est, e, slack)
     errs = bench.sampled_errors(jobs, xs, g)
     for j, x, st, e, es in zip(jobs, xs, sts, errs, sk):
         case = next(c for c in g["cases"]
@@ -76,3 +81,27 @@ def test_point12_10x4_matches_oracle(precision, tol):
         assert es <= 0.85 * tol, (j["mu"], j["spin"], j["colour"], es)
     print(f"{precision}: max full-vector rel err (sketch estimate) {max(sk):.2e}, max sampled {max(errs):.2e} "
           f"over {len(errs)} sources")
+
+
+def test_spurious_two_sided_ritz_value_does_not_mistune_p():
+    """Regression (p_opt, Eq. popt): at k = 620 the GPU's two-sided H_k of the
+    mu = 0.2 source (spin 3, colour 1) held a Ritz value at |theta| = 13.7,
+    beyond the bound ||A|| <= 1 + kappa (6 sqrt 2 + 2 sqrt(2 cosh 2 mu)) = 3.38
+    that holds for every eigenvalue of A.  Taken for z_max it set p = 0.93
+    instead of 2.27 and the error to 6.5e-7.  z_max is now capped at the bound:
+    the reported z_max never exceeds it, and the result is within 5e-9 of the
+    converged reference (full-vector sketch estimate)."""
+    import torch
+    import bench
+    import paper_0912_4457_amd as nks
+    from gpu_common import ctx
+    lats, jobs = bench.make_jobs(nks, torch, ctx(), "fp64")
+    j = [j for j in jobs if j["mu"] == 0.2 and j["spin"] == 3 and j["colour"] == 1][0]
+    x, st = nks.sign_apply(j["lat"], j["b"], k=620, ell=64)
+    kappa = 1.0 / (8.0 - 2.0 * bench.M0)
+    bound = 1.0 + kappa * (6.0 * np.sqrt(2.0) + 2.0 * np.sqrt(2.0 * np.cosh(2.0 * 0.2)))
+    assert st["status"] == 0 and st["z_max"] <= bound * (1 + 1e-12)
+    e = bench.errors_vs_sketch([j], [x], bench.sketch_golden())[0]
+    print(f"k=620 mu=0.2 (3,1): p {st['p_used']:.4f}, z_max {st['z_max']:.4f} (cap {bound:.4f}, "
+          f"{'engaged' if abs(st['z_max'] - bound) <= 1e-12 * bound else 'not engaged'}), error {e:.2e}")
+    assert e <= 5e-9

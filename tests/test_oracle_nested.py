@@ -225,6 +225,39 @@ def test_ritz_extremes_skip_the_one_ritz_value_in_the_gap():
         assert np.sum(np.abs(w) < 0.1) == 1
 
 
+def test_zmax_cap_ignores_a_spurious_ritz_value():
+    """A two-sided H_k without reorthogonalisation can hold a Ritz value far
+    outside A's spectrum (seen at |theta| = 13.7 against ||A|| <= 3.38 on a
+    10^4 lattice, where it took p from 2.27 to 0.94 and the nested error at
+    ell = 64 from 1e-10 to 2e-7).  Modelled here by a ghost: the oracle's own
+    H_200 with one more, almost decoupled diagonal entry of 20.  Uncapped,
+    z_max = 20 takes p_opt (Eq. popt) to 0.83 and the nested result at ell = 64
+    is far less accurate; capped at dirac.norm_bound it is as accurate as on
+    H_200 itself.  Hermitian Ritz values never reach the cap."""
+    op = _op(0.3, dims=(4, 4, 4, 4), eps=0.5, seed=4401)
+    kr = krylov.two_sided_lanczos(op.matvec, op.rmatvec, I.gaussian_source(op.dims, 4402).ravel(), 200)
+    al = np.append(kr.alpha, 20.0)
+    be = np.append(kr.beta, 1e-9)
+    ga = np.append(kr.gamma, 1e-9)
+    h = np.diag(al) + np.diag(be, -1) + np.diag(ga, 1)
+    exact = signfun.sign_eig(h, hermitian=False)[:, 0]
+    zmin, zmax = nested.ritz_extremes(al, be, ga, False)
+    assert zmax > 19.0
+    zmin_c, zmax_c = nested.ritz_extremes(al, be, ga, False, op.norm_bound)
+    assert zmin_c == zmin and zmax_c == op.norm_bound
+    c_plain, i_plain = nested.nested_coefficients(al, be, ga, False, 64)
+    c_cap, i_cap = nested.nested_coefficients(al, be, ga, False, 64, zmax_bound=op.norm_bound)
+    e_plain = np.linalg.norm(c_plain - exact) / np.linalg.norm(exact)
+    e_cap = np.linalg.norm(c_cap - exact) / np.linalg.norm(exact)
+    c_ref, _ = nested.nested_coefficients(kr.alpha, kr.beta, kr.gamma, False, 64)
+    e_ref = np.linalg.norm(c_ref - signfun.sign_eig(kr.H(), hermitian=False)[:, 0]) / np.linalg.norm(exact)
+    assert e_cap < 0.1 * e_plain and e_cap < 10 * e_ref + 1e-13
+    # Hermitian: Ritz values lie in A's field of values, inside the bound
+    oph = _op(0.0, dims=(4, 4, 4, 4), eps=0.5, seed=4401)
+    krh = krylov.lanczos(oph.matvec, I.gaussian_source(oph.dims, 4402).ravel(), 120)
+    assert nested.ritz_extremes(krh.alpha, krh.beta, krh.beta, True)[1] < oph.norm_bound
+
+
 def test_pure_gauge_nested_full_method():
     dims = (4, 4, 4, 4)
     g = I.random_su3_field(dims, 44)

@@ -104,3 +104,22 @@ def test_plane_wave_eigenvector_free_field():
     spin = vecs[:, 0]
     psi = (phase[:, None, None] * spin[None, :, None] * np.array([1, 0, 0])[None, None, :]).ravel()
     assert np.linalg.norm(op.matvec(psi) - w[0] * psi) < 1e-12 * np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("kind", ["su3", "unit"])
+@pytest.mark.parametrize("mu", [0.0, 0.2, 0.5])
+def test_norm_bound_holds(kind, mu):
+    """|lambda| <= ||A||_2 <= dirac.norm_bound(m0, mu) (Sec. 2 operator), and the
+    bound is within 30 % of ||A||_2 on the free field (so it can cap a
+    spectrum estimate without cutting into it by much)."""
+    dims = (4, 2, 2, 4)                  # even extents: the free field reaches momentum pi
+    u = I.su3_links(dims, 0.6, 77) if kind == "su3" else I.unit_links(dims)
+    op = dirac.Operator(u, dims, 1.6, mu)
+    a = op.dense()
+    smax = np.linalg.norm(a, 2)
+    bound = dirac.norm_bound(1.6, mu)
+    assert op.norm_bound == bound
+    assert np.abs(np.linalg.eigvals(a)).max() <= smax * (1 + 1e-12)
+    assert smax <= bound
+    if kind == "unit" and mu == 0.0:
+        assert smax >= 0.7 * bound
