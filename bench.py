@@ -40,7 +40,8 @@ MUS = (0.0, 0.2)
 K_MU, ELL = {0.0: 520, 0.2: 620}, 64   # outer size per mu (Lanczos / two-sided), nested size
 INFLIGHT = 1          # batches in flight on separate streams in the timed region
 SERIAL_GROUPS = False    # --serial-groups
-KERNEL_SOURCES = ("paper_0912_4457_amd/csrc/wilson.h", "paper_0912_4457_amd/csrc/outer.hip")
+KERNEL_SOURCES = ("paper_0912_4457_amd/csrc/wilson.h", "paper_0912_4457_amd/csrc/outer.hip",
+                  "paper_0912_4457_amd/csrc/nks_internal.h")
 
 
 def log(msg):
