@@ -65,7 +65,10 @@ def test_predicted_k_is_verified_and_accepted(mu):
 
 @pytest.mark.parametrize("mu", [0.0, 0.3])
 def test_short_prediction_falls_back_to_checkpoints(mu):
-    tol = 1e-10
+    # two-sided on this 3072-dimensional operator the weighted coefficient
+    # change between checkpoints levels off near 2e-11 (k = 1000, the cap):
+    # tol = 1e-10 would put the tol/4 acceptance on that rounding floor
+    tol = 1e-10 if mu == 0.0 else 1e-9
     kp = plain_k(mu, tol)
     assert kp >= 300
     x, st = _learned(mu, tol, constant_net(125, 16))     # k target 140: far too short
