@@ -608,10 +608,14 @@ constexpr size_t GRAPH_CACHE = 4;
 
 // Graph mode: the kernel sequence of a batch is captured once (on a private
 // stream) and replayed; the job table is uploaded before every replay.  The
-// key is the table itself (every pointer, size and option of every job).
+// key is the table itself (every pointer, size and option of every job)
+// except each job's b and x: the kernels read those from the uploaded table
+// only, so new source and output buffers replay the same graph.
 int enqueue_graph(nks_ctx* ctx, const Plan& P, const std::vector<JobDesc>& descs, char* ws, hipStream_t s) {
-    std::vector<char> key(sizeof(JobDesc) * descs.size());
-    std::memcpy(key.data(), descs.data(), key.size());
+    std::vector<JobDesc> kd(descs);
+    for (auto& d : kd) { d.b = nullptr; d.x = nullptr; }
+    std::vector<char> key(sizeof(JobDesc) * kd.size());
+    std::memcpy(key.data(), kd.data(), key.size());
     auto put = [&key](const void* p, size_t n) {
         key.insert(key.end(), static_cast<const char*>(p), static_cast<const char*>(p) + n);
     };
